@@ -1,0 +1,170 @@
+"""Oracle for the X-engine correlation path -- TEST INFRASTRUCTURE ONLY.
+
+A plain CPU implementation (``xcorr_oracle.c``: int64 loops over channel,
+input pair and time sample, FP64 normalisation) with a ctypes wrapper.
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import it.  It shares no code with the HIP path and never
+imports the product package.
+
+``build()`` compiles the C file with gcc (OpenMP over the outer loops);
+``load()`` returns an :class:`Oracle` bound to a built library, building it
+first when none exists.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "xcorr_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_p = ctypes.c_void_p
+
+
+def build(src: str = SRC, out: str = LIB, extra: Sequence[str] = ()) -> str:
+    """Compile the oracle into a shared library; returns its path."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c99",
+           "-Wall", "-Wextra", *extra, src, "-o", out + ".tmp"]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_p)
+
+
+class Oracle:
+    """numpy-level access to one built oracle library."""
+
+    def __init__(self, path: str):
+        self.path = path
+        lib = ctypes.CDLL(path)
+        self._lib = lib
+        lib.oracle_tri_index.restype = _i64
+        lib.oracle_tri_index.argtypes = [_i64, _i64, _i64]
+        lib.oracle_num_pairs.restype = _i64
+        lib.oracle_num_pairs.argtypes = [_i64]
+        lib.oracle_decode.restype = None
+        lib.oracle_decode.argtypes = [ctypes.c_uint8, ctypes.POINTER(_i32),
+                                      ctypes.POINTER(_i32)]
+        lib.oracle_valid_counts.restype = None
+        lib.oracle_valid_counts.argtypes = [_p, _i32, _i32, _i32, _p]
+        for name in ("oracle_correlate", "oracle_accumulate"):
+            fn = getattr(lib, name)
+            fn.restype = None
+            fn.argtypes = [_p, _p, _i32, _i32, _i32, _i32, _p, _p]
+        lib.oracle_correlate_full.restype = None
+        lib.oracle_correlate_full.argtypes = [_p, _p, _i32, _i32, _i32, _i32, _p]
+        lib.oracle_correlate_pairs.restype = None
+        lib.oracle_correlate_pairs.argtypes = [_p, _p, _i32, _i32, _i32, _i32,
+                                               _p, _p, _p, _i64, _p]
+        lib.oracle_normalize.restype = None
+        lib.oracle_normalize.argtypes = [_p, _p, _i32, _i32, _p]
+
+    # -- helpers ---------------------------------------------------------
+    @staticmethod
+    def _frame_args(packed: np.ndarray, mask: Optional[np.ndarray], B: int):
+        packed = np.ascontiguousarray(packed, dtype=np.uint8)
+        if packed.ndim != 3:
+            raise ValueError("packed must be [T][F][N]")
+        T, F, N = packed.shape
+        if mask is not None:
+            mask = np.ascontiguousarray(mask, dtype=np.uint8)
+            if mask.shape != (F, (T + B - 1) // B):
+                raise ValueError("mask must be [F][ceil(T/B)]")
+        return packed, mask, N, F, T
+
+    # -- API ---------------------------------------------------------------
+    def tri_index(self, N: int, i: int, j: int) -> int:
+        return int(self._lib.oracle_tri_index(N, i, j))
+
+    def num_pairs(self, N: int) -> int:
+        return int(self._lib.oracle_num_pairs(N))
+
+    def decode(self, byte: int) -> Tuple[int, int]:
+        re, im = _i32(), _i32()
+        self._lib.oracle_decode(byte, ctypes.byref(re), ctypes.byref(im))
+        return re.value, im.value
+
+    def valid_counts(self, mask: Optional[np.ndarray], F: int, T: int, B: int) -> np.ndarray:
+        out = np.zeros(F, dtype=np.int64)
+        if mask is not None:
+            mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self._lib.oracle_valid_counts(_ptr(mask), F, T, B, _ptr(out))
+        return out
+
+    def correlate(self, packed, mask=None, B: int = 256):
+        packed, mask, N, F, T = self._frame_args(packed, mask, B)
+        vis = np.zeros((F, N * (N + 1) // 2, 2), dtype=np.int64)
+        cnt = np.zeros(F, dtype=np.int64)
+        self._lib.oracle_correlate(_ptr(packed), _ptr(mask), N, F, T, B,
+                                   _ptr(vis), _ptr(cnt))
+        return vis, cnt
+
+    def accumulate(self, packed, mask, B: int, vis: np.ndarray, cnt: np.ndarray) -> None:
+        packed, mask, N, F, T = self._frame_args(packed, mask, B)
+        if vis.dtype != np.int64 or not vis.flags.c_contiguous or \
+                vis.shape != (F, N * (N + 1) // 2, 2):
+            raise ValueError("vis must be contiguous int64 [F][P][2]")
+        if cnt.dtype != np.int64 or cnt.shape != (F,):
+            raise ValueError("count must be int64 [F]")
+        self._lib.oracle_accumulate(_ptr(packed), _ptr(mask), N, F, T, B,
+                                    _ptr(vis), _ptr(cnt))
+
+    def correlate_full(self, packed, mask=None, B: int = 256) -> np.ndarray:
+        packed, mask, N, F, T = self._frame_args(packed, mask, B)
+        out = np.zeros((F, N, N, 2), dtype=np.int64)
+        self._lib.oracle_correlate_full(_ptr(packed), _ptr(mask), N, F, T, B, _ptr(out))
+        return out
+
+    def correlate_pairs(self, packed, mask, B: int, fs, is_, js) -> np.ndarray:
+        packed, mask, N, F, T = self._frame_args(packed, mask, B)
+        fs = np.ascontiguousarray(fs, dtype=np.int32)
+        is_ = np.ascontiguousarray(is_, dtype=np.int32)
+        js = np.ascontiguousarray(js, dtype=np.int32)
+        n = fs.size
+        if not (is_.size == n and js.size == n):
+            raise ValueError("index arrays differ in length")
+        if n and (fs.min() < 0 or fs.max() >= F or is_.min() < 0 or js.min() < 0
+                  or is_.max() >= N or js.max() >= N):
+            raise ValueError("index out of range")
+        out = np.zeros((n, 2), dtype=np.int64)
+        self._lib.oracle_correlate_pairs(_ptr(packed), _ptr(mask), N, F, T, B,
+                                         _ptr(fs), _ptr(is_), _ptr(js), n, _ptr(out))
+        return out
+
+    def normalize(self, vis: np.ndarray, cnt: np.ndarray) -> np.ndarray:
+        vis = np.ascontiguousarray(vis, dtype=np.int64)
+        cnt = np.ascontiguousarray(cnt, dtype=np.int64)
+        F, P, two = vis.shape
+        N = int(round((np.sqrt(8 * P + 1) - 1) / 2))
+        if two != 2 or N * (N + 1) // 2 != P or cnt.shape != (F,):
+            raise ValueError("vis must be [F][N(N+1)/2][2], count [F]")
+        out = np.zeros((F, P, 2), dtype=np.float32)
+        self._lib.oracle_normalize(_ptr(vis), _ptr(cnt), N, F, _ptr(out))
+        return out
+
+
+_cached: Optional[Oracle] = None
+
+
+def load(path: Optional[str] = None) -> Oracle:
+    """The oracle bound to ``path`` (default: the in-tree build, built on
+    first use when missing)."""
+    global _cached
+    if path is not None:
+        return Oracle(path)
+    if _cached is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        _cached = Oracle(LIB)
+    return _cached

@@ -1,0 +1,180 @@
+/*
+ * Oracle for the X-engine correlation path.  TEST INFRASTRUCTURE ONLY.
+ *
+ * A deliberately plain, slow CPU implementation of what the correlator
+ * computes.  Only the test suite, the smoke check and the benchmark's CPU
+ * baseline may build, load or call it; the product library never links,
+ * includes or calls anything in this directory, and this file includes no
+ * header of the product.
+ *
+ * The method reaches an exact result with a plain definition, so the oracle
+ * is that definition written out, with int64 accumulators:
+ *
+ *   sample    x[t][f][i] = a + i*b, one byte per complex sample, high nibble
+ *             a+8, low nibble b+8 (4+4-bit complex values, Sec. I and
+ *             Sec. II-A: all inputs of one band take one byte each).
+ *   loss      a sample whose packet block is flagged lost contributes
+ *             nothing, whatever its bytes hold (Sec. II-A.2: lost data are
+ *             zeros).  Blocks are B samples of one channel.
+ *   correlate for each channel f and 0 <= i <= j < N,
+ *             V[f][i][j] = sum over valid t of x[t][f][i] * conj(x[t][f][j])
+ *             stored as a row-major packed upper triangle including the
+ *             diagonal, index(i,j) = i*N - i*(i-1)/2 + (j-i), (re, im).
+ *   count     n[f] = number of valid samples of channel f (Sec. II-C: packet
+ *             loss is tracked as one counter added to every point).
+ *   accumulate adds V and n of a frame into running sums: the correlation
+ *             kernels add into the output of the previous run (Sec. II-B).
+ *   normalize out = (float)((double)V / (double)n), 0 when n == 0: the
+ *             fraction of lost data is applied to the correlation matrix at
+ *             the end of the integration (Sec. II-C).
+ *
+ * Loop order follows the definition: channel, i, j >= i, then the sum over
+ * t.  OpenMP may split the (f, i) loop across threads; every sum is exact,
+ * so the thread count does not change any result.
+ */
+#include <stdint.h>
+#include <stddef.h>
+
+/* value of the high (real) nibble and of the low (imaginary) nibble */
+static int re_part(uint8_t byte) { return (int)(byte >> 4) - 8; }
+static int im_part(uint8_t byte) { return (int)(byte & 15) - 8; }
+
+/* 1 when sample t of channel f is valid (its block is not flagged lost) */
+static int sample_valid(const uint8_t *mask, int F, int T, int B, int f, int t)
+{
+    (void)F;
+    if (mask == NULL)
+        return 1;
+    int64_t nblk = ((int64_t)T + B - 1) / B;
+    return mask[(int64_t)f * nblk + t / B] == 0;
+}
+
+int64_t oracle_tri_index(int64_t N, int64_t i, int64_t j)
+{
+    return i * N - i * (i - 1) / 2 + (j - i);
+}
+
+int64_t oracle_num_pairs(int64_t N)
+{
+    return N * (N + 1) / 2;
+}
+
+void oracle_decode(uint8_t byte, int32_t *re, int32_t *im)
+{
+    *re = re_part(byte);
+    *im = im_part(byte);
+}
+
+/* n[f] = number of valid samples of channel f in this frame */
+void oracle_valid_counts(const uint8_t *mask, int32_t F, int32_t T, int32_t B,
+                         int64_t *count)
+{
+    for (int f = 0; f < F; ++f) {
+        int64_t n = 0;
+        for (int t = 0; t < T; ++t)
+            n += sample_valid(mask, F, T, B, f, t);
+        count[f] = n;
+    }
+}
+
+/* sum over valid t of x_i * conj(x_j) for one channel and one pair */
+static void pair_sum(const uint8_t *packed, const uint8_t *mask, int N, int F,
+                     int T, int B, int f, int i, int j, int64_t *re_out,
+                     int64_t *im_out)
+{
+    int64_t re = 0, im = 0;
+    for (int t = 0; t < T; ++t) {
+        if (!sample_valid(mask, F, T, B, f, t))
+            continue;
+        const uint8_t *row = packed + ((int64_t)t * F + f) * N;
+        int ai = re_part(row[i]), bi = im_part(row[i]);
+        int aj = re_part(row[j]), bj = im_part(row[j]);
+        /* (ai + i bi)(aj - i bj) = (ai aj + bi bj) + i (bi aj - ai bj) */
+        re += (int64_t)ai * aj + (int64_t)bi * bj;
+        im += (int64_t)bi * aj - (int64_t)ai * bj;
+    }
+    *re_out = re;
+    *im_out = im;
+}
+
+/* V over one frame, overwriting vis [F][P][2] and count [F] */
+void oracle_correlate(const uint8_t *packed, const uint8_t *mask, int32_t N,
+                      int32_t F, int32_t T, int32_t B, int64_t *vis,
+                      int64_t *count)
+{
+    int64_t P = oracle_num_pairs(N);
+#pragma omp parallel for collapse(2) schedule(dynamic)
+    for (int f = 0; f < F; ++f)
+        for (int i = 0; i < N; ++i)
+            for (int j = i; j < N; ++j) {
+                int64_t *out = vis + ((int64_t)f * P + oracle_tri_index(N, i, j)) * 2;
+                pair_sum(packed, mask, N, F, T, B, f, i, j, &out[0], &out[1]);
+            }
+    oracle_valid_counts(mask, F, T, B, count);
+}
+
+/* running integration: vis += V(frame), count += n(frame) */
+void oracle_accumulate(const uint8_t *packed, const uint8_t *mask, int32_t N,
+                       int32_t F, int32_t T, int32_t B, int64_t *vis,
+                       int64_t *count)
+{
+    int64_t P = oracle_num_pairs(N);
+#pragma omp parallel for collapse(2) schedule(dynamic)
+    for (int f = 0; f < F; ++f)
+        for (int i = 0; i < N; ++i)
+            for (int j = i; j < N; ++j) {
+                int64_t re, im;
+                pair_sum(packed, mask, N, F, T, B, f, i, j, &re, &im);
+                int64_t *out = vis + ((int64_t)f * P + oracle_tri_index(N, i, j)) * 2;
+                out[0] += re;
+                out[1] += im;
+            }
+    for (int f = 0; f < F; ++f) {
+        int64_t n = 0;
+        for (int t = 0; t < T; ++t)
+            n += sample_valid(mask, F, T, B, f, t);
+        count[f] += n;
+    }
+}
+
+/* every ordered pair (i, j), full matrix [F][N][N][2]; used for checks
+ * that need both triangles (Hermitian symmetry) */
+void oracle_correlate_full(const uint8_t *packed, const uint8_t *mask,
+                           int32_t N, int32_t F, int32_t T, int32_t B,
+                           int64_t *vis_full)
+{
+#pragma omp parallel for collapse(2) schedule(dynamic)
+    for (int f = 0; f < F; ++f)
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) {
+                int64_t *out = vis_full + (((int64_t)f * N + i) * N + j) * 2;
+                pair_sum(packed, mask, N, F, T, B, f, i, j, &out[0], &out[1]);
+            }
+}
+
+/* V for a list of (f, i, j) triples only, out [n][2]; lets a test check a
+ * sample of baselines of a frame too large for the full loop */
+void oracle_correlate_pairs(const uint8_t *packed, const uint8_t *mask,
+                            int32_t N, int32_t F, int32_t T, int32_t B,
+                            const int32_t *fs, const int32_t *is,
+                            const int32_t *js, int64_t n, int64_t *out)
+{
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t k = 0; k < n; ++k)
+        pair_sum(packed, mask, N, F, T, B, fs[k], is[k], js[k], &out[2 * k],
+                 &out[2 * k + 1]);
+}
+
+/* out [F][P][2] = V / n in double, rounded once to float; 0 when n == 0 */
+void oracle_normalize(const int64_t *vis, const int64_t *count, int32_t N,
+                      int32_t F, float *out)
+{
+    int64_t P = oracle_num_pairs(N);
+    for (int f = 0; f < F; ++f) {
+        int64_t n = count[f];
+        for (int64_t p = 0; p < 2 * P; ++p) {
+            int64_t k = (int64_t)f * 2 * P + p;
+            out[k] = n == 0 ? 0.0f : (float)((double)vis[k] / (double)n);
+        }
+    }
+}

@@ -1,0 +1,340 @@
+"""Seeded synthetic inputs for the X-engine correlator.
+
+This module only *makes* inputs: complex voltages drawn from numpy's PCG64,
+quantised to the 4+4-bit offset encoding, laid out as the frames the
+correlator consumes, plus packet-loss masks.  It holds none of the
+correlation arithmetic and imports nothing else from this package, so the
+oracle (test infrastructure) and the HIP path can both consume its bytes
+without sharing any code of the method.
+
+Data layout (Sec. II-A, the packet carries all inputs of each band for a few
+time samples and is used by the GPU unmodified):
+
+* ``packed``  ``uint8[T][F][N]`` -- time-major, then channel, then input.
+  One byte per complex sample: high nibble = real part, low nibble =
+  imaginary part, each offset-encoded ``0..15`` meaning ``-8..7``.
+* ``mask``    ``uint8[F][ceil(T/B)]`` -- one flag per channel and packet block
+  of ``B`` samples, non-zero = the block was lost.  The last block may be
+  partial.  Lost samples are written as ``0x88`` (value zero, the paper's
+  zero fill, Sec. II-A.2) unless a test asks for garbage bytes there.
+
+Workload recipes (sizes from Sec. I, Sec. II-A, Sec. III and Table I: N=256
+inputs, 64 channels per server, 32-256 MB frames, N=16 and N=2048 scaling
+points) are the functions ``tiny``, ``pathfinder``, ``large_n``,
+``batched`` and ``streaming_streams`` below.  No public dataset exists for
+this method; these synthetic frames stand in for live F-engine data.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+#: byte that encodes the complex value 0 + 0i (both nibbles = 8)
+ZERO_BYTE = 0x88
+
+#: per-recipe default seeds
+SEEDS = {"tiny": 101, "pathfinder": 102, "large_n": 103, "batched": 104,
+         "streaming": 105}
+
+#: time samples drawn per noise chunk; part of the recipe (fixes draw order)
+CHUNK = 1024
+
+
+@dataclasses.dataclass
+class Frame:
+    """One frame of packed samples plus its loss mask."""
+
+    packed: np.ndarray          # uint8 [T][F][N]
+    mask: Optional[np.ndarray]  # uint8 [F][nblk] or None (= nothing lost)
+    N: int
+    F: int
+    T: int
+    B: int
+    name: str = ""
+    seed: int = 0
+
+    @property
+    def nblk(self) -> int:
+        return (self.T + self.B - 1) // self.B
+
+    @property
+    def nbytes(self) -> int:
+        return self.T * self.F * self.N
+
+
+def encode(re: np.ndarray, im: np.ndarray) -> np.ndarray:
+    """Integers in [-8, 7] -> offset-encoded bytes (hi nibble re, lo nibble im)."""
+    re = np.asarray(re, dtype=np.int16)
+    im = np.asarray(im, dtype=np.int16)
+    if re.size and (re.min() < -8 or re.max() > 7 or im.min() < -8 or im.max() > 7):
+        raise ValueError("components must lie in [-8, 7]")
+    return (((re + 8) << 4) | (im + 8)).astype(np.uint8)
+
+
+def quantize(z_re: np.ndarray, z_im: np.ndarray, clip: int = 7) -> np.ndarray:
+    """Round half-to-even, clip each component to [-clip, clip], encode."""
+    re = np.clip(np.rint(z_re), -clip, clip).astype(np.int16)
+    im = np.clip(np.rint(z_im), -clip, clip).astype(np.int16)
+    return encode(re, im)
+
+
+def nblocks(T: int, B: int) -> int:
+    return (T + B - 1) // B
+
+
+def bernoulli_mask(rng: np.random.Generator, F: int, T: int, B: int,
+                   p: float) -> np.ndarray:
+    """Independent loss per (channel, block) with probability p."""
+    return (rng.random((F, nblocks(T, B))) < p).astype(np.uint8)
+
+
+def gilbert_elliott_mask(rng: np.random.Generator, F: int, nblk: int,
+                         rate: float, mean_burst: float = 4.0,
+                         cap: float = 0.10) -> np.ndarray:
+    """Bursty loss: two-state Markov chain per channel over blocks.
+
+    The bad state lasts ``mean_burst`` blocks on average and the long-run
+    fraction of lost blocks is ``rate``; each channel's loss in this frame
+    is capped at ``cap`` of its blocks (extra lost blocks are un-flagged
+    from the end).
+    """
+    mask = np.zeros((F, nblk), dtype=np.uint8)
+    if rate <= 0:
+        return mask
+    p_bg = 1.0 / mean_burst                      # bad -> good
+    p_gb = rate * p_bg / max(1e-12, 1.0 - rate)  # good -> bad
+    state = rng.random(F) < rate
+    for b in range(nblk):
+        mask[:, b] = state
+        u = rng.random(F)
+        state = np.where(state, u >= p_bg, u < p_gb)
+    limit = int(math.floor(cap * nblk))
+    for f in range(F):
+        lost = np.flatnonzero(mask[f])
+        if lost.size > limit:
+            mask[f, lost[limit:]] = 0
+    return mask
+
+
+def fill_lost(packed: np.ndarray, mask: Optional[np.ndarray], B: int,
+              fill: str = "zero", rng: Optional[np.random.Generator] = None) -> None:
+    """Overwrite the samples of lost blocks in place.
+
+    ``fill='zero'`` writes 0x88 (the zero value, as the network thread of
+    Sec. II-A.2 does); ``fill='garbage'`` writes random bytes, which a
+    correct correlator must ignore because it applies the mask itself.
+    """
+    if mask is None:
+        return
+    T, F, N = packed.shape
+    if fill == "garbage" and rng is None:
+        rng = np.random.default_rng(0)
+    for f, b in zip(*np.nonzero(mask)):
+        t0, t1 = int(b) * B, min(T, (int(b) + 1) * B)
+        if fill == "zero":
+            packed[t0:t1, f, :] = ZERO_BYTE
+        elif fill == "garbage":
+            packed[t0:t1, f, :] = rng.integers(0, 256, (t1 - t0, N), dtype=np.uint8)
+        else:
+            raise ValueError(fill)
+
+
+# ---------------------------------------------------------------------------
+# generic helpers for tests
+# ---------------------------------------------------------------------------
+
+def random_bytes_frame(seed: int, N: int, F: int, T: int, B: int = 256,
+                       p_loss: float = 0.0, fill: str = "garbage") -> Frame:
+    """Uniform random bytes (all 256 codes, including -8 components)."""
+    rng = np.random.default_rng(seed)
+    packed = rng.integers(0, 256, (T, F, N), dtype=np.uint8)
+    mask = bernoulli_mask(rng, F, T, B, p_loss) if p_loss > 0 else None
+    fill_lost(packed, mask, B, fill, rng)
+    return Frame(packed, mask, N, F, T, B, "random_bytes", seed)
+
+
+def gaussian_frame(seed: int, N: int, F: int, T: int, B: int = 256,
+                   sigma: float = 2.5, p_loss: float = 0.0,
+                   fill: str = "zero") -> Frame:
+    """Gaussian noise per component, rounded and clipped to [-7, 7]."""
+    rng = np.random.default_rng(seed)
+    mask = bernoulli_mask(rng, F, T, B, p_loss) if p_loss > 0 else None
+    packed = np.empty((T, F, N), dtype=np.uint8)
+    for t0 in range(0, T, CHUNK):
+        t1 = min(T, t0 + CHUNK)
+        re = rng.standard_normal((t1 - t0, F, N), dtype=np.float32) * sigma
+        im = rng.standard_normal((t1 - t0, F, N), dtype=np.float32) * sigma
+        packed[t0:t1] = quantize(re, im)
+    fill_lost(packed, mask, B, fill, rng)
+    return Frame(packed, mask, N, F, T, B, "gaussian", seed)
+
+
+# ---------------------------------------------------------------------------
+# the workload recipes
+# ---------------------------------------------------------------------------
+
+def tiny(seed: int = SEEDS["tiny"]) -> Frame:
+    """N=16 inputs, 8 channels, 256 samples, sigma=2.5 noise, no loss."""
+    fr = gaussian_frame(seed, N=16, F=8, T=256, B=256, sigma=2.5)
+    fr.mask = np.zeros((8, 1), dtype=np.uint8)
+    fr.name = "tiny_n16_f8_t256"
+    return fr
+
+
+def pathfinder(seed: int = SEEDS["pathfinder"], N: int = 256, F: int = 64,
+               T: int = 16384, B: int = 256, p_loss: float = 0.01,
+               tone_amp: float = 2.0, sigma: float = 2.5,
+               fill: str = "zero") -> Frame:
+    """One server's share of the pathfinder: N=256, 64 channels, 16384 samples.
+
+    Noise sigma=2.5 per component plus one sky tone per channel,
+    ``s_f(t) = A exp(i(2 pi nu_f t + phi_f))``, seen by input i through a
+    complex gain ``g_i = r_i exp(i theta_i)`` with r ~ U(0.5, 1.5),
+    theta ~ U(0, 2 pi) shared by all channels.  1% of the 256-sample blocks
+    of each channel are lost.  Draw order: gains, tone parameters, mask,
+    then noise chunk by chunk (real, then imaginary).
+    """
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.5, 1.5, N)
+    theta = rng.uniform(0.0, 2 * np.pi, N)
+    gain = (r * np.exp(1j * theta)).astype(np.complex64)          # [N]
+    nu = rng.uniform(-0.5, 0.5, F)
+    phi = rng.uniform(0.0, 2 * np.pi, F)
+    mask = bernoulli_mask(rng, F, T, B, p_loss)
+    packed = np.empty((T, F, N), dtype=np.uint8)
+    for t0 in range(0, T, CHUNK):
+        t1 = min(T, t0 + CHUNK)
+        t = np.arange(t0, t1, dtype=np.float64)[:, None]
+        tone = (tone_amp * np.exp(1j * (2 * np.pi * nu[None, :] * t + phi[None, :])))
+        sky = tone.astype(np.complex64)[:, :, None] * gain[None, None, :]
+        re = rng.standard_normal((t1 - t0, F, N), dtype=np.float32) * sigma + sky.real
+        im = rng.standard_normal((t1 - t0, F, N), dtype=np.float32) * sigma + sky.imag
+        packed[t0:t1] = quantize(re, im)
+    fill_lost(packed, mask, B, fill, np.random.default_rng(seed + 7919))
+    return Frame(packed, mask, N, F, T, B, f"pathfinder_n{N}_f{F}_t{T}", seed)
+
+
+def large_n(seed: int = SEEDS["large_n"], N: int = 2048, F: int = 16,
+            T: int = 8192, B: int = 256, p_loss: float = 0.005,
+            n_src: int = 4, sigma: float = 2.5) -> Frame:
+    """Large-N scaling point: N=2048, 16 channels, 8192 samples.
+
+    Noise sigma=2.5 plus ``n_src`` point sources; source k emits
+    ``s_k(f, t) ~ CN(0, 1)`` and reaches input i with phase
+    ``exp(i phi_{k,i})``, phi ~ U(0, 2 pi).  0.5% of 256-sample blocks lost.
+    """
+    rng = np.random.default_rng(seed)
+    phase = np.exp(1j * rng.uniform(0.0, 2 * np.pi, (n_src, N))).astype(np.complex64)
+    mask = bernoulli_mask(rng, F, T, B, p_loss)
+    packed = np.empty((T, F, N), dtype=np.uint8)
+    for t0 in range(0, T, CHUNK):
+        t1 = min(T, t0 + CHUNK)
+        n = t1 - t0
+        s = ((rng.standard_normal((n, F, n_src)) + 1j * rng.standard_normal((n, F, n_src)))
+             / np.sqrt(2.0)).astype(np.complex64)
+        sky = np.einsum("tfk,ki->tfi", s, phase)
+        re = rng.standard_normal((n, F, N), dtype=np.float32) * sigma + sky.real
+        im = rng.standard_normal((n, F, N), dtype=np.float32) * sigma + sky.imag
+        packed[t0:t1] = quantize(re, im)
+    fill_lost(packed, mask, B, "zero")
+    return Frame(packed, mask, N, F, T, B, f"large_n{N}_f{F}_t{T}", seed)
+
+
+@dataclasses.dataclass
+class InstanceSpec:
+    N: int
+    T: int
+    sigma: float
+    p_loss: float
+    seed: int
+
+
+def batched_specs(seed: int = SEEDS["batched"], n_inst: int = 128,
+                  t_scale: float = 1.0,
+                  n_choices=(64, 128, 256, 512, 1024)) -> List[InstanceSpec]:
+    """Uneven single-channel instances: N from ``n_choices``, T log-uniform
+    in [1024, 65536] rounded to a multiple of 256 (times ``t_scale``, for
+    cheaper test runs), sigma ~ U(1.5, 3.5), loss p ~ U(0, 0.05)."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for k in range(n_inst):
+        N = int(rng.choice(n_choices))
+        T = 256 * int(round(math.exp(rng.uniform(math.log(1024), math.log(65536))) / 256))
+        T = max(1, int(round(T * t_scale)))
+        sigma = float(rng.uniform(1.5, 3.5))
+        p = float(rng.uniform(0.0, 0.05))
+        specs.append(InstanceSpec(N, T, sigma, p, int(seed * 100003 + k)))
+    return specs
+
+
+def instance_frame(spec: InstanceSpec, B: int = 256) -> Frame:
+    fr = gaussian_frame(spec.seed, spec.N, 1, spec.T, B, spec.sigma, spec.p_loss)
+    if fr.mask is None:
+        fr.mask = np.zeros((1, fr.nblk), dtype=np.uint8)
+    fr.name = f"inst_n{spec.N}_t{spec.T}"
+    return fr
+
+
+def batched(seed: int = SEEDS["batched"], n_inst: int = 128,
+            t_scale: float = 1.0) -> List[Frame]:
+    return [instance_frame(s) for s in batched_specs(seed, n_inst, t_scale)]
+
+
+@dataclasses.dataclass
+class StreamSpec:
+    stream_id: int
+    N: int
+    F: int
+    T: int                 # samples per frame
+    frames_per_integration: int
+    loss_rate: float       # long-run fraction of lost blocks
+    rate_bps: float        # offered input rate, bits of 4-bit sky data per second
+    seed: int
+
+    @property
+    def frame_bytes(self) -> int:
+        return self.T * self.F * self.N
+
+    @property
+    def frame_rate(self) -> float:
+        """Mean frames per second for the offered rate (8 bits per sample)."""
+        return self.rate_bps / (8.0 * self.frame_bytes)
+
+
+def streaming_streams(seed: int = SEEDS["streaming"], n_streams: int = 8,
+                      total_bps: float = 51.2e9, T: int = 4096,
+                      n_choices=(128, 256, 512), f_range=(16, 64),
+                      l_range=(10, 100), max_loss: float = 0.05) -> List[StreamSpec]:
+    """Several concurrent streams sharing one GPU; each is offered an equal
+    share of ``total_bps`` (the per-host rate of Table I by default)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n_streams):
+        N = int(rng.choice(n_choices))
+        F = int(rng.integers(f_range[0], f_range[1] + 1))
+        L = int(rng.integers(l_range[0], l_range[1] + 1))
+        loss = float(rng.uniform(0.0, max_loss))
+        out.append(StreamSpec(s, N, F, T, L, loss, total_bps / n_streams,
+                              int(seed * 1000 + s)))
+    return out
+
+
+def stream_frame(spec: StreamSpec, index: int, B: int = 256, sigma: float = 2.5,
+                 burst: float = 4.0, cap: float = 0.10) -> Frame:
+    """Frame ``index`` of a stream: Gaussian noise plus bursty block loss."""
+    rng = np.random.default_rng([spec.seed, index])
+    nblk = nblocks(spec.T, B)
+    mask = gilbert_elliott_mask(rng, spec.F, nblk, spec.loss_rate, burst, cap)
+    packed = np.empty((spec.T, spec.F, spec.N), dtype=np.uint8)
+    for t0 in range(0, spec.T, CHUNK):
+        t1 = min(spec.T, t0 + CHUNK)
+        re = rng.standard_normal((t1 - t0, spec.F, spec.N), dtype=np.float32) * sigma
+        im = rng.standard_normal((t1 - t0, spec.F, spec.N), dtype=np.float32) * sigma
+        packed[t0:t1] = quantize(re, im)
+    fill_lost(packed, mask, B, "zero")
+    return Frame(packed, mask, spec.N, spec.F, spec.T, B,
+                 f"stream{spec.stream_id}_frame{index}", spec.seed)

@@ -1,0 +1,334 @@
+"""Pins that tie the oracle to facts other than its own code.
+
+Each ``pin_*`` takes an :class:`oracle.Oracle` and raises ``AssertionError``
+when the oracle disagrees with what the mathematics or the method fixes:
+
+* a library routine (numpy complex128 matrix product) and pure-Python
+  complex arithmetic on small inputs built from *values*, never from the
+  oracle's own decoding of bytes;
+* closed forms (constant input, quarter-rate tone, all-(-8-8i) overflow
+  edge, tone normalised after loss);
+* invariants (Hermitian symmetry, real non-negative autocorrelations,
+  linearity across frames, nibble swap = conjugation, i*x and -x leave V
+  unchanged, input permutation permutes V, garbage in lost blocks changes
+  nothing);
+* exact rational arithmetic for the normalisation's rounding.
+
+``tests/test_oracle_pins.py`` runs them on the oracle; the planted-mistake
+test runs them on altered copies of it and requires each copy to fail one.
+"""
+
+from __future__ import annotations
+
+import itertools
+from fractions import Fraction
+
+import numpy as np
+
+from paper_1503_06189_amd import synth
+
+
+# ---------------------------------------------------------------------------
+# helpers that build frames from complex *values* (no decoding involved)
+# ---------------------------------------------------------------------------
+
+def _values(rng, shape, lo=-8, hi=7):
+    re = rng.integers(lo, hi + 1, shape)
+    im = rng.integers(lo, hi + 1, shape)
+    return re, im
+
+
+def _frame_from_values(re, im):
+    return synth.encode(re, im)
+
+
+def _expand_mask(mask, T, B):
+    """[F][nblk] block flags -> [T][F] boolean validity, by repetition."""
+    if mask is None:
+        return None
+    rep = np.repeat(mask != 0, B, axis=1)[:, :T]   # [F][T]
+    return ~rep.T
+
+
+def _numpy_vis(re, im, valid=None):
+    """Upper-triangle V from values with numpy's complex matrix product."""
+    T, F, N = re.shape
+    x = re.astype(np.complex128) + 1j * im.astype(np.complex128)
+    if valid is not None:
+        x = x * valid[:, :, None]
+    out = []
+    iu, ju = np.triu_indices(N)
+    for f in range(F):
+        X = x[:, f, :]                       # [T][N]
+        V = X.T @ X.conj()                   # V[i][j] = sum_t x_i conj(x_j)
+        out.append(np.stack([V[iu, ju].real, V[iu, ju].imag], axis=-1))
+    return np.rint(np.array(out)).astype(np.int64)
+
+
+# ---------------------------------------------------------------------------
+# pins
+# ---------------------------------------------------------------------------
+
+def pin_decode_roundtrip(orc):
+    """Every (re, im) in [-8, 7]^2 survives the independent encoder, and the
+    256 byte codes map one-to-one onto those 256 values."""
+    seen = set()
+    for re, im in itertools.product(range(-8, 8), repeat=2):
+        b = int(_frame_from_values(np.array(re), np.array(im)))
+        assert orc.decode(b) == (re, im), (re, im, b)
+        seen.add(orc.decode(b))
+    assert len({orc.decode(b) for b in range(256)}) == 256
+    assert len(seen) == 256
+
+
+def pin_tri_index(orc):
+    """Row-major packed upper triangle incl. diagonal is a bijection onto
+    0..P-1 and consecutive along each row."""
+    for N in (1, 2, 3, 16, 256):
+        P = N * (N + 1) // 2
+        assert orc.num_pairs(N) == P
+        idx = [orc.tri_index(N, i, j) for i in range(N) for j in range(i, N)]
+        assert idx == list(range(P)), N
+
+
+def pin_numpy_matmul(orc):
+    """Random values incl. -8, random loss with garbage in lost blocks:
+    oracle == numpy complex128 X^T conj(X) over the valid samples (exact,
+    every partial sum is an integer far below 2^53)."""
+    rng = np.random.default_rng(11)
+    for (N, F, T, B, p) in [(1, 1, 1, 1, 0.0), (3, 2, 7, 2, 0.3), (8, 3, 64, 8, 0.25),
+                            (5, 2, 33, 4, 0.5), (16, 1, 40, 256, 0.0)]:
+        re, im = _values(rng, (T, F, N))
+        packed = _frame_from_values(re, im)
+        mask = (rng.random((F, (T + B - 1) // B)) < p).astype(np.uint8)
+        valid = _expand_mask(mask, T, B)
+        # garbage in lost blocks: the oracle must not read it
+        noise = rng.integers(0, 256, packed.shape, dtype=np.uint8)
+        packed = np.where(valid[:, :, None], packed, noise).astype(np.uint8)
+        vis, cnt = orc.correlate(packed, mask, B)
+        exp = _numpy_vis(re, im, valid)
+        assert np.array_equal(vis, exp), (N, F, T, B)
+        assert np.array_equal(cnt, valid.sum(axis=0)), (N, F, T, B)
+
+
+def pin_python_brute_force(orc):
+    """Pure-Python complex loops on a handful of samples."""
+    rng = np.random.default_rng(12)
+    T, F, N = 5, 2, 4
+    re, im = _values(rng, (T, F, N))
+    vis, _ = orc.correlate(_frame_from_values(re, im), None, 4)
+    p = 0
+    for i in range(N):
+        for j in range(i, N):
+            for f in range(F):
+                s = 0j
+                for t in range(T):
+                    xi = complex(int(re[t, f, i]), int(im[t, f, i]))
+                    xj = complex(int(re[t, f, j]), int(im[t, f, j]))
+                    s += xi * xj.conjugate()
+                assert vis[f, p, 0] == s.real and vis[f, p, 1] == s.imag, (f, i, j)
+            p += 1
+
+
+def pin_hermitian_autocorr(orc):
+    """Full matrix: V_ji = conj(V_ij); Im V_ii = 0; Re V_ii = sum |x_i|^2;
+    the packed triangle is the upper half of the full matrix."""
+    rng = np.random.default_rng(13)
+    T, F, N, B = 48, 2, 6, 16
+    re, im = _values(rng, (T, F, N))
+    mask = np.array([[0, 1, 0], [0, 0, 1]], dtype=np.uint8)
+    packed = _frame_from_values(re, im)
+    full = orc.correlate_full(packed, mask, B)
+    vis, _ = orc.correlate(packed, mask, B)
+    valid = _expand_mask(mask, T, B)
+    assert np.array_equal(full[..., 0], full[..., 0].transpose(0, 2, 1))
+    assert np.array_equal(full[..., 1], -full[..., 1].transpose(0, 2, 1))
+    power = ((re.astype(np.int64) ** 2 + im.astype(np.int64) ** 2) * valid[:, :, None]).sum(0)
+    for f in range(F):
+        assert np.array_equal(np.diagonal(full[f, :, :, 0]), power[f])
+        assert not np.diagonal(full[f, :, :, 1]).any()
+        iu, ju = np.triu_indices(N)
+        assert np.array_equal(full[f, iu, ju], vis[f])
+
+
+def pin_constant_input(orc):
+    """x_i(t) = c_i for every t: V_ij = n c_i conj(c_j), n = valid count."""
+    rng = np.random.default_rng(14)
+    T, F, N, B = 40, 3, 7, 8
+    cr, ci = _values(rng, (F, N))
+    re = np.broadcast_to(cr, (T, F, N))
+    im = np.broadcast_to(ci, (T, F, N))
+    mask = np.zeros((F, 5), dtype=np.uint8)
+    mask[1, 2] = 1
+    mask[2, :] = 1
+    vis, cnt = orc.correlate(_frame_from_values(re, im), mask, B)
+    assert list(cnt) == [40, 32, 0]
+    p = 0
+    for i in range(N):
+        for j in range(i, N):
+            for f in range(F):
+                c_i = complex(int(cr[f, i]), int(ci[f, i]))
+                c_j = complex(int(cr[f, j]), int(ci[f, j]))
+                v = cnt[f] * c_i * c_j.conjugate()
+                assert (vis[f, p, 0], vis[f, p, 1]) == (v.real, v.imag)
+            p += 1
+
+
+def _tone(rng, T, F, N):
+    """x_i(t) = g_i * (1j)^t: multiplying by 1j swaps/negates the
+    components, so values stay integers in [-7, 7]."""
+    gr, gi = _values(rng, (F, N), -7, 7)
+    g = gr + 1j * gi
+    ph = (1j) ** np.arange(T)
+    x = ph[:, None, None] * g[None]
+    re = np.rint(x.real).astype(np.int64)
+    im = np.rint(x.imag).astype(np.int64)
+    return g, re, im
+
+
+def pin_single_tone_and_normalize(orc):
+    """Quarter-rate tone: V_ij = n g_i conj(g_j) (the phase cancels); after
+    loss, V/n = g_i conj(g_j) exactly."""
+    rng = np.random.default_rng(15)
+    T, F, N, B = 64, 2, 5, 4
+    g, re, im = _tone(rng, T, F, N)
+    mask = (rng.random((F, T // B)) < 0.4).astype(np.uint8)
+    vis, cnt = orc.correlate(_frame_from_values(re, im), mask, B)
+    out = orc.normalize(vis, cnt)
+    iu, ju = np.triu_indices(N)
+    for f in range(F):
+        G = np.outer(g[f], g[f].conj())[iu, ju]
+        assert np.array_equal(vis[f, :, 0], cnt[f] * G.real.astype(np.int64))
+        assert np.array_equal(vis[f, :, 1], cnt[f] * G.imag.astype(np.int64))
+        assert np.array_equal(out[f, :, 0], G.real.astype(np.float32))
+        assert np.array_equal(out[f, :, 1], G.imag.astype(np.float32))
+
+
+def pin_linearity(orc):
+    """accumulate(F1); accumulate(F2) == correlate(F1 then F2 in time);
+    also a start from non-zero sums (resume from a snapshot)."""
+    rng = np.random.default_rng(16)
+    N, F, B = 6, 2, 8
+    T1, T2 = 24, 40
+    fr = synth.random_bytes_frame(17, N, F, T1 + T2, B, p_loss=0.3)
+    m1, m2 = fr.mask[:, :T1 // B], fr.mask[:, T1 // B:]
+    full_v, full_n = orc.correlate(fr.packed, fr.mask, B)
+    v = np.zeros_like(full_v)
+    n = np.zeros_like(full_n)
+    orc.accumulate(fr.packed[:T1], m1, B, v, n)
+    orc.accumulate(fr.packed[T1:], m2, B, v, n)
+    assert np.array_equal(v, full_v) and np.array_equal(n, full_n)
+    start_v = rng.integers(-1000, 1000, v.shape).astype(np.int64)
+    start_n = rng.integers(0, 1000, n.shape).astype(np.int64)
+    v2, n2 = start_v.copy(), start_n.copy()
+    orc.accumulate(fr.packed, fr.mask, B, v2, n2)
+    assert np.array_equal(v2, start_v + full_v) and np.array_equal(n2, start_n + full_n)
+
+
+def pin_symmetries(orc):
+    """Nibble swap (x -> i conj x) conjugates V for every byte; i*x and -x
+    leave V unchanged; permuting inputs permutes V."""
+    rng = np.random.default_rng(18)
+    T, F, N, B = 32, 2, 6, 8
+    packed = rng.integers(0, 256, (T, F, N), dtype=np.uint8)
+    mask = (rng.random((F, T // B)) < 0.3).astype(np.uint8)
+    v, _ = orc.correlate(packed, mask, B)
+    swapped = ((packed >> 4) | (packed << 4)).astype(np.uint8)
+    vs, _ = orc.correlate(swapped, mask, B)
+    assert np.array_equal(vs[..., 0], v[..., 0]) and np.array_equal(vs[..., 1], -v[..., 1])
+
+    re, im = _values(rng, (T, F, N), -7, 7)
+    v0, _ = orc.correlate(_frame_from_values(re, im), mask, B)
+    vi, _ = orc.correlate(_frame_from_values(-im, re), mask, B)      # i * x
+    vn, _ = orc.correlate(_frame_from_values(-re, -im), mask, B)     # -x
+    assert np.array_equal(vi, v0) and np.array_equal(vn, v0)
+
+    perm = rng.permutation(N)
+    full = orc.correlate_full(packed, mask, B)
+    fullp = orc.correlate_full(packed[:, :, perm], mask, B)
+    assert np.array_equal(fullp, full[:, perm][:, :, perm])
+
+
+def pin_loss_and_counts(orc):
+    """Lost blocks: garbage == zero fill; counts == samples outside lost
+    blocks, including a partial last block; an all-lost channel gives 0."""
+    for (N, F, T, B, p) in [(4, 3, 50, 8, 0.4), (3, 2, 17, 5, 0.5), (2, 4, 9, 256, 0.5)]:
+        seed = 19 + T
+        zero = synth.random_bytes_frame(seed, N, F, T, B, p_loss=p, fill="zero")
+        junk = zero.packed.copy()
+        synth.fill_lost(junk, zero.mask, B, "garbage", np.random.default_rng(seed))
+        vz, nz = orc.correlate(zero.packed, zero.mask, B)
+        vj, nj = orc.correlate(junk, zero.mask, B)
+        assert np.array_equal(vz, vj) and np.array_equal(nz, nj)
+        valid = _expand_mask(zero.mask, T, B)
+        assert np.array_equal(nz, valid.sum(axis=0))
+        assert np.array_equal(orc.valid_counts(zero.mask, F, T, B), nz)
+    mask = np.ones((2, 3), dtype=np.uint8)
+    mask[1, 1] = 0
+    packed = np.full((20, 2, 3), 0x00, dtype=np.uint8)
+    v, n = orc.correlate(packed, mask, 8)
+    assert list(n) == [0, 8] and not v[0].any()
+    assert (v[1, :, 0] == 128 * 8).all() and not v[1, :, 1].any()
+
+
+def pin_overflow_edge(orc):
+    """Every byte 0x00 (x = -8-8i): Re V = 128 n, Im V = 0, exactly, at the
+    largest frame length whose sums still fit int32 (16,777,215)."""
+    T = 16_777_215
+    packed = np.zeros((T, 1, 2), dtype=np.uint8)
+    vis, cnt = orc.correlate(packed, None, 256)
+    assert cnt[0] == T
+    assert (vis[0, :, 0] == 128 * T).all() and not vis[0, :, 1].any()
+    assert 128 * T < 2 ** 31
+
+
+def pin_pairs_subset(orc):
+    """The sampled-pairs entry equals the full matrix for any (f, i, j),
+    including i > j."""
+    fr = synth.random_bytes_frame(23, 7, 3, 30, 4, p_loss=0.3)
+    full = orc.correlate_full(fr.packed, fr.mask, 4)
+    rng = np.random.default_rng(24)
+    fs = rng.integers(0, 3, 50)
+    is_ = rng.integers(0, 7, 50)
+    js = rng.integers(0, 7, 50)
+    got = orc.correlate_pairs(fr.packed, fr.mask, 4, fs, is_, js)
+    assert np.array_equal(got, full[fs, is_, js])
+
+
+def pin_normalize_rounding(orc):
+    """V/n rounded to float32 lies within half an ulp (plus the double
+    step's 2^-53) of the exact rational V/n; n = 0 gives exactly 0."""
+    rng = np.random.default_rng(25)
+    F, N = 4, 20
+    P = N * (N + 1) // 2
+    vis = rng.integers(-2 ** 31 + 1, 2 ** 31 - 1, (F, P, 2)).astype(np.int64)
+    vis[1] = rng.integers(-2 ** 26, 2 ** 26, (P, 2))
+    cnt = np.array([3, 16_777_213, 0, 7919], dtype=np.int64)
+    out = orc.normalize(vis, cnt)
+    assert not out[2].any()
+    for f in (0, 1, 3):
+        for p in range(P):
+            for c in range(2):
+                exact = Fraction(int(vis[f, p, c]), int(cnt[f]))
+                got = Fraction(float(out[f, p, c]))
+                m, e = np.frexp(np.float32(float(exact)))
+                half_ulp = Fraction(2) ** (int(e) - 25)
+                assert abs(got - exact) <= half_ulp * (1 + Fraction(1, 2 ** 28)), \
+                    (f, p, c, float(exact), float(got))
+
+
+PINS = [
+    pin_decode_roundtrip,
+    pin_tri_index,
+    pin_numpy_matmul,
+    pin_python_brute_force,
+    pin_hermitian_autocorr,
+    pin_constant_input,
+    pin_single_tone_and_normalize,
+    pin_linearity,
+    pin_symmetries,
+    pin_loss_and_counts,
+    pin_overflow_edge,
+    pin_pairs_subset,
+    pin_normalize_rounding,
+]
