@@ -1,0 +1,152 @@
+/*
+ * xengine.h -- C ABI of the MI355X (gfx950) X-engine correlator.
+ *
+ * The correlator is the X stage of an FX correlator (Sec. I): for every
+ * frequency channel it multiplies every input against every other input
+ * and integrates over time (Sec. II-B), then the integrated matrix is
+ * normalised for samples lost on the way (Sec. II-C).
+ *
+ * Data formats (all buffers are device memory unless stated otherwise, all
+ * owned by the caller; the library never frees or keeps them):
+ *
+ *   packed     uint8 [T][F][N], time-major, then channel, then input: the
+ *              channelised data of the UDP packets placed unmodified into a
+ *              frame (Sec. II-A).  One byte per complex sample: high nibble
+ *              = real part, low nibble = imaginary part, each offset-encoded
+ *              0..15 meaning -8..7 (4+4-bit complex, Sec. I).
+ *   loss_mask  uint8 [F][ceil(T/B)], one flag per channel and block of B
+ *              samples, non-zero = lost.  The last block may be partial.
+ *              A lost sample contributes nothing whatever its bytes hold
+ *              (lost data are zeroed, Sec. II-A.2; the kernel applies the
+ *              mask itself).  NULL = nothing lost.
+ *   vis        int32 [F][N(N+1)/2][2], per channel the upper triangle of
+ *              V[i][j] = sum over valid t of x_i * conj(x_j), i <= j,
+ *              row-major packed: index(i,j) = i*N - i*(i-1)/2 + (j-i),
+ *              (real, imaginary) interleaved.  8-byte aligned.
+ *   count      int64 [F], valid samples integrated per channel (the packet
+ *              loss counter of Sec. II-C).  8-byte aligned.
+ *   out        float32 [F][N(N+1)/2][2], normalised visibilities.
+ *
+ * Integer sums are exact.  |Re V| <= 128 and |Im V| <= 120 per sample, so
+ * int32 holds any integration of at most XE_MAX_SAMPLES valid samples; a
+ * single call accepts at most that many samples (XE_ERR_OVERFLOW), and
+ * keeping a running integration within it across calls is the caller's job.
+ *
+ * Calls are asynchronous: they validate their arguments on the host,
+ * enqueue kernels on `stream` (a hipStream_t; NULL = the null stream of the
+ * handle's device) and return.  They allocate nothing and do not
+ * synchronise, so they may be captured into a HIP graph.  Argument errors
+ * are reported before anything is enqueued; launch errors are reported as
+ * XE_ERR_HIP; errors during execution surface at the caller's next
+ * synchronisation.  A handle is not thread-safe: use one per host thread.
+ * Nothing is thrown across the ABI.
+ */
+#ifndef XENGINE_H
+#define XENGINE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xe_handle_s *xe_handle;
+typedef int32_t xe_status;
+
+#define XE_OK 0
+#define XE_ERR_ARG (-1)         /* bad size, null pointer, bad handle       */
+#define XE_ERR_ALIGN (-2)       /* vis / count / out not 8-byte aligned     */
+#define XE_ERR_OVERFLOW (-3)    /* T > XE_MAX_SAMPLES (int32 sums could wrap)*/
+#define XE_ERR_WORKSPACE (-4)   /* batch does not fit the handle's workspace*/
+#define XE_ERR_HIP (-5)         /* HIP runtime error; see xe_last_error     */
+#define XE_ERR_UNSUPPORTED (-6) /* device is not gfx950                      */
+#define XE_ERR_NO_DEVICE (-7)   /* validation-only handle: nothing launched */
+
+#define XE_MAX_N 4096
+#define XE_MAX_SAMPLES 16777215 /* 128 * this < 2^31 */
+#define XE_DEVICE_NONE (-1)
+
+/* Create a handle on HIP device `hip_device`.  `workspace_bytes` of device
+ * memory is allocated here, once, for batched work lists (0 = a default of
+ * a few MB); no later call allocates.  With hip_device == XE_DEVICE_NONE the
+ * handle is validation-only: every compute call checks its arguments and
+ * then returns XE_ERR_NO_DEVICE without touching memory (for host tests).
+ * Errors: XE_ERR_ARG (out == NULL), XE_ERR_HIP, XE_ERR_UNSUPPORTED. */
+xe_status xe_create(xe_handle *out, int32_t hip_device, size_t workspace_bytes);
+
+/* Free the handle and its workspace; NULL is accepted.  Work still queued
+ * on the caller's streams must have finished. */
+xe_status xe_destroy(xe_handle h);
+
+/* Static text for a status code. */
+const char *xe_status_string(xe_status s);
+
+/* Text of the last error seen on this handle ("" if none); valid until the
+ * next call on the handle. */
+const char *xe_last_error(xe_handle h);
+
+/* Correlate one frame and OVERWRITE vis and count with its sums
+ * (Sec. II-B: correlation of a staged frame; Sec. II-C: the loss counter).
+ * 1 <= N <= XE_MAX_N, F >= 1, 1 <= T <= XE_MAX_SAMPLES, B >= 1. */
+xe_status xe_correlate_frame(xe_handle h, const uint8_t *packed,
+                             const uint8_t *loss_mask, int32_t N, int32_t F,
+                             int32_t T, int32_t B, int32_t *vis,
+                             int64_t *count, void *stream);
+
+/* Correlate one frame and ADD its sums into vis and count: the kernels
+ * extend the integration held in device memory, with no copy back per
+ * frame (Sec. II-B).  Same arguments and limits as xe_correlate_frame. */
+xe_status xe_accumulate(xe_handle h, const uint8_t *packed,
+                        const uint8_t *loss_mask, int32_t N, int32_t F,
+                        int32_t T, int32_t B, int32_t *vis, int64_t *count,
+                        void *stream);
+
+/* out = (float)((double)vis / (double)count[f]) element-wise, rounded once
+ * to nearest; 0 where count[f] == 0 (Sec. II-C: the lost fraction applied
+ * to the correlation matrix at the end of an integration).  vis and out may
+ * not overlap. */
+xe_status xe_normalize(xe_handle h, const int32_t *vis, const int64_t *count,
+                       int32_t N, int32_t F, float *out, void *stream);
+
+/* One correlator instance of a batch: a frame of one sub-array with its own
+ * N, F, T and B, accumulated into its own vis and count.  Pointers are
+ * device pointers; the array of instances itself is host memory. */
+typedef struct {
+    const uint8_t *packed;
+    const uint8_t *loss_mask;
+    int32_t N, F, T, B;
+    int32_t *vis;
+    int64_t *count;
+} xe_instance;
+
+/* Accumulate every instance of the batch in one persistent launch (the
+ * paper pre-queues whole chains of operations to hide launch latency,
+ * Sec. II-B; several streams share one GPU, Sec. II).  Each instance is
+ * validated as for xe_accumulate.  The work list is written into the
+ * handle's workspace with one asynchronous host-to-device copy on `stream`;
+ * XE_ERR_WORKSPACE when it does not fit.  The list must stay unchanged until
+ * the launch has run, so a second batch on the same handle is ordered after
+ * the first on the same stream (or the caller synchronises). */
+xe_status xe_accumulate_batch(xe_handle h, const xe_instance *inst,
+                              int32_t n_inst, void *stream);
+
+/* How the library splits one frame into workgroups (host only, no GPU):
+ * validates (N, F, T, B) as the compute calls do. */
+typedef struct {
+    int32_t blocks;          /* ceil(N / 32): 32-input tile edge            */
+    int32_t groups;          /* workgroup tile groups per channel          */
+    int32_t splits;          /* time chunks per (channel, group)           */
+    int32_t steps_per_split; /* 32-sample steps per chunk                  */
+    int64_t workgroups;      /* channels * groups * splits                 */
+    int64_t mfma_tiles;      /* 32x32 tiles computed per channel           */
+} xe_plan_info;
+
+xe_status xe_plan_query(int32_t N, int32_t F, int32_t T, int32_t B,
+                        int32_t n_cu, xe_plan_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XENGINE_H */

@@ -1,0 +1,112 @@
+// plan.hpp -- how one frame is split into workgroups (host and device).
+//
+// The triangle of 32x32 input-block tiles (I <= J) of each channel is cut
+// into "super-blocks" of 8x8 tiles (256 x 256 inputs).  A workgroup of four
+// waves takes one tile group:
+//   * a diagonal super-block: a triangle of 36 tiles.  Wave w takes tile
+//     rows w and 7-w (8-w and w+1 tiles), so every wave runs 9 tiles;
+//   * half of an off-diagonal super-block: 4 tile rows x 8 tile columns.
+//     Wave w takes rows 2(w/2), 2(w/2)+1 and columns 4(w%2)..+3 (8 tiles).
+// Super-blocks at the edge of the triangle are padded: input blocks past
+// ceil(N/32) are staged as zeros and their tiles are computed but never
+// stored, so every wave has a fixed, compile-time tile pattern.
+// With ns = ceil(blocks / 8) super-rows there are ns diagonal groups and
+// ns(ns-1)/2 off-diagonal super-blocks of two halves each: ns^2 groups.
+// Each workgroup integrates its tiles over one chunk of the frame's time
+// samples; chunks of the same tiles are added into the output.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define XE_HD __host__ __device__
+#else
+#define XE_HD
+#endif
+
+namespace xe {
+
+constexpr int kBlk = 32;          // inputs per tile edge (one 32x32 MFMA)
+constexpr int kStep = 32;         // samples staged per step
+constexpr int kSuper = 8;         // tile blocks per super-block edge
+constexpr int kMaxSlots = 12;     // input blocks staged per workgroup
+constexpr int kTilesPerWave = 9;  // 32x32 accumulator tiles per wave
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+
+// One tile group, in scalars (no arrays: kept in scalar registers on the
+// device).  Slot s of the staged blocks holds input block
+//   diagonal:      rbase + s                       (s < nslots)
+//   off-diagonal:  rbase + s for s < 4, cbase + s - 4 otherwise
+struct Group {
+    int diag;
+    int rbase, cbase;
+    int nslots;
+};
+
+XE_HD inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+XE_HD inline int super_rows(int nb) { return ceil_div(nb, kSuper); }
+
+XE_HD inline int groups_per_channel(int nb) {
+    int ns = super_rows(nb);
+    return ns * ns;
+}
+
+// off-diagonal super-block number p (row-major over R < C) -> (R, C)
+XE_HD inline void offdiag_pair(int ns, int p, int *R, int *C) {
+    int r = 0;
+    while (p >= ns - 1 - r) {
+        p -= ns - 1 - r;
+        ++r;
+    }
+    *R = r;
+    *C = r + 1 + p;
+}
+
+XE_HD inline Group make_group(int nb, int gid) {
+    Group g;
+    int ns = super_rows(nb);
+    if (gid < ns) {
+        g.diag = 1;
+        g.rbase = g.cbase = gid * kSuper;
+        g.nslots = kSuper;  // blocks past the last one are staged as zeros
+    } else {
+        int q = gid - ns;
+        int R, C;
+        offdiag_pair(ns, q / 2, &R, &C);
+        g.diag = 0;
+        g.rbase = R * kSuper + 4 * (q % 2);  // R is never the last super-row
+        g.cbase = C * kSuper;
+        g.nslots = 4 + kSuper;
+    }
+    return g;
+}
+
+XE_HD inline int slot_block(const Group &g, int s) {
+    return (g.diag || s < 4) ? g.rbase + s : g.cbase + (s - 4);
+}
+
+// 32x32 tiles computed per channel: 36 per diagonal group (8 x 9), 32 per
+// off-diagonal half (4 x 8); padded tiles past N included.
+inline int64_t tiles_per_channel(int nb) {
+    int64_t ns = super_rows(nb);
+    return ns * 36 + ns * (ns - 1) * 32;
+}
+
+// Time split: enough workgroups to cover `n_cu` compute units once, but
+// at least `min_steps` staged steps per chunk.
+inline void choose_split(int64_t units, int steps, int n_cu, int *splits,
+                         int *steps_per_split) {
+    const int min_steps = 8;
+    int64_t want = (n_cu + units - 1) / units;
+    int64_t cap = steps / min_steps;
+    if (cap < 1) cap = 1;
+    int64_t s = want < cap ? want : cap;
+    if (s < 1) s = 1;
+    int sps = ceil_div(steps, (int)s);
+    *steps_per_split = sps;
+    *splits = ceil_div(steps, sps);
+}
+
+}  // namespace xe

@@ -1,0 +1,218 @@
+"""HIP path vs the oracle, element by element (GPU).
+
+Integer visibilities and counts must be bit-exact; normalised float32 must
+stay within 1e-6 relative of the oracle's FP64 normalisation (both divide in
+double and round once, so in practice they are identical).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_06189_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def xe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_06189_amd import xengine
+    xengine.lib()   # fails loudly if the library is missing
+    return xengine
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_gpu(xe, fr, normalize=False):
+    packed = _dev(fr.packed)
+    mask = _dev(fr.mask) if fr.mask is not None else None
+    vis, cnt = xe.correlate_frame(packed, mask, fr.B)
+    out = xe.normalize(vis, cnt) if normalize else None
+    torch.cuda.synchronize()
+    res = (vis.cpu().numpy().astype(np.int64), cnt.cpu().numpy())
+    if normalize:
+        res = res + (out.cpu().numpy(),)
+    return res
+
+
+def check_full(xe, orc, fr, normalize=True):
+    _say(f"case {fr.name} N={fr.N} F={fr.F} T={fr.T} B={fr.B} seed={fr.seed}")
+    got = run_gpu(xe, fr, normalize)
+    ev, en = orc.correlate(fr.packed, fr.mask, fr.B)
+    assert np.array_equal(got[1], en), "counts differ"
+    bad = np.argwhere(got[0] != ev)
+    assert bad.size == 0, f"{len(bad)} visibilities differ, first {bad[:5].tolist()}"
+    if normalize:
+        eo = orc.normalize(ev, en)
+        np.testing.assert_allclose(got[2], eo, rtol=1e-6, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# small and ragged shapes, whole output
+# ---------------------------------------------------------------------------
+
+def test_tiny_config(xe, orc):
+    check_full(xe, orc, synth.tiny())
+
+
+SHAPES = [
+    # N, F, T, B, p_loss
+    (1, 1, 1, 1, 0.0),
+    (2, 3, 5, 2, 0.3),
+    (3, 2, 33, 4, 0.3),
+    (16, 4, 31, 256, 0.0),
+    (31, 2, 100, 7, 0.2),
+    (32, 2, 64, 16, 0.1),
+    (33, 3, 97, 32, 0.2),
+    (64, 2, 300, 50, 0.1),
+    (100, 2, 257, 64, 0.2),
+    (255, 1, 129, 128, 0.1),
+    (256, 2, 1000, 256, 0.05),
+    (257, 1, 200, 3, 0.2),
+    (300, 1, 95, 1000, 0.0),
+    (513, 1, 70, 16, 0.2),
+]
+
+
+@pytest.mark.parametrize("N,F,T,B,p", SHAPES, ids=[f"N{s[0]}_F{s[1]}_T{s[2]}_B{s[3]}" for s in SHAPES])
+def test_shapes_random_bytes(xe, orc, N, F, T, B, p):
+    """Uniform random bytes (every code, -8 included), garbage in lost
+    blocks, ragged N, T and B."""
+    fr = synth.random_bytes_frame(1000 + N + T, N, F, T, B, p_loss=p, fill="garbage")
+    check_full(xe, orc, fr)
+
+
+def test_all_lost_channel_and_no_mask(xe, orc):
+    fr = synth.random_bytes_frame(5, 40, 3, 300, 64, p_loss=0.0)
+    fr.mask = np.zeros((3, 5), dtype=np.uint8)
+    fr.mask[1, :] = 1
+    check_full(xe, orc, fr)
+    fr.mask = None
+    check_full(xe, orc, fr)
+
+
+def test_accumulate_linearity(xe, orc):
+    """accumulate(F1) + accumulate(F2) on the device == oracle of F1 then F2."""
+    N, F, B = 96, 3, 32
+    fr = synth.random_bytes_frame(77, N, F, 640, B, p_loss=0.1)
+    T1 = 224
+    vis, cnt = xe.new_accumulators(N, F)
+    xe.accumulate(_dev(fr.packed[:T1]), _dev(fr.mask[:, :T1 // B]), B, vis, cnt)
+    xe.accumulate(_dev(fr.packed[T1:]), _dev(fr.mask[:, T1 // B:]), B, vis, cnt)
+    torch.cuda.synchronize()
+    ev, en = orc.correlate(fr.packed, fr.mask, B)
+    assert np.array_equal(vis.cpu().numpy().astype(np.int64), ev)
+    assert np.array_equal(cnt.cpu().numpy(), en)
+
+
+def test_unaligned_packed_pointer(xe, orc):
+    """A frame that starts at an odd address takes the byte-load path."""
+    fr = synth.random_bytes_frame(9, 64, 2, 100, 16, p_loss=0.2)
+    buf = torch.zeros(fr.packed.size + 1, dtype=torch.uint8, device="cuda")
+    buf[1:] = _dev(fr.packed.reshape(-1))
+    packed = buf[1:].view(fr.T, fr.F, fr.N)
+    assert packed.data_ptr() % 4 == 1
+    vis, cnt = xe.correlate_frame(packed, _dev(fr.mask), fr.B)
+    torch.cuda.synchronize()
+    ev, en = orc.correlate(fr.packed, fr.mask, fr.B)
+    assert np.array_equal(vis.cpu().numpy().astype(np.int64), ev)
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads: sampled baselines + properties that hold at any size
+# ---------------------------------------------------------------------------
+
+def _sample_pairs(rng, N, F, n):
+    fs = rng.integers(0, F, n)
+    i = rng.integers(0, N, n)
+    j = rng.integers(0, N, n)
+    lo, hi = np.minimum(i, j), np.maximum(i, j)
+    # always include the corners and the diagonal
+    fs = np.concatenate([fs, [0, F - 1, F - 1, 0]])
+    lo = np.concatenate([lo, [0, 0, N - 1, N - 1]])
+    hi = np.concatenate([hi, [0, N - 1, N - 1, N - 1]])
+    return fs, lo, hi
+
+
+def check_sampled(xe, orc, fr, n_pairs=3000):
+    _say(f"case {fr.name} N={fr.N} F={fr.F} T={fr.T} B={fr.B} seed={fr.seed} (sampled)")
+    vis, cnt, out = run_gpu(xe, fr, normalize=True)
+    N, F = fr.N, fr.F
+    # counts: samples outside lost blocks (numpy, independent of the oracle)
+    if fr.mask is not None:
+        lost_per_blk = np.minimum(fr.B, fr.T - np.arange(fr.nblk) * fr.B)
+        exp_n = fr.T - (fr.mask.astype(np.int64) * lost_per_blk[None, :]).sum(1)
+    else:
+        exp_n = np.full(F, fr.T)
+    assert np.array_equal(cnt, exp_n)
+    rng = np.random.default_rng(fr.seed)
+    fs, i, j = _sample_pairs(rng, N, F, n_pairs)
+    exp = orc.correlate_pairs(fr.packed, fr.mask, fr.B, fs, i, j)
+    idx = i * N - i * (i - 1) // 2 + (j - i)
+    got = vis[fs, idx]
+    bad = np.argwhere((got != exp).any(axis=1))
+    assert bad.size == 0, f"{len(bad)} sampled baselines differ: {bad[:5].ravel().tolist()}"
+    # autocorrelations: real, non-negative, at every input of every channel
+    di = np.arange(N)
+    dia = di * N - di * (di - 1) // 2
+    assert not vis[:, dia, 1].any()
+    assert (vis[:, dia, 0] >= 0).all()
+    # normalisation on the sampled baselines: each sample as a one-input
+    # "channel" of the oracle's normalisation
+    eo = orc.normalize(exp.reshape(-1, 1, 2), exp_n[fs])
+    np.testing.assert_allclose(out[fs, idx], eo[:, 0, :], rtol=1e-6, atol=0)
+
+
+def test_pathfinder_full_size(xe, orc):
+    """N=256, 64 channels, 16384 samples, 1% block loss: the bench workload."""
+    check_sampled(xe, orc, synth.pathfinder())
+
+
+def test_large_n_full_size(xe, orc):
+    """N=2048, 16 channels, 8192 samples, 0.5% loss."""
+    check_sampled(xe, orc, synth.large_n(), n_pairs=2000)
+
+
+def test_max_n(xe, orc):
+    fr = synth.random_bytes_frame(4096, 4096, 1, 40, 16, p_loss=0.2)
+    check_sampled(xe, orc, fr, n_pairs=2000)
+
+
+def test_overflow_edge(xe):
+    """All bytes 0x00 (x = -8-8i) over the longest frame a call accepts:
+    Re V = 128 T = 2,147,483,520 (fits int32), Im V = 0 everywhere."""
+    T, F, N = 16_777_215, 1, 16
+    _say(f"case overflow_edge N={N} F={F} T={T}")
+    packed = torch.zeros((T, F, N), dtype=torch.uint8, device="cuda")
+    vis, cnt = xe.correlate_frame(packed, None, 256)
+    torch.cuda.synchronize()
+    v = vis.cpu().numpy()
+    assert int(cnt.cpu()[0]) == T
+    assert (v[..., 0] == 128 * T).all() and not v[..., 1].any()
+    del packed
+
+
+def test_bad_arguments_raise(xe):
+    packed = torch.zeros((4, 1, 8), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        xe.correlate_frame(packed, torch.zeros((1, 3), dtype=torch.uint8, device="cuda"), 2)
+    with pytest.raises(xe.XEngineError):
+        xe.correlate_frame(torch.zeros((0, 1, 8), dtype=torch.uint8, device="cuda"), None, 2)
