@@ -2,18 +2,23 @@
 //
 // The triangle of 32x32 input-block tiles (I <= J) of each channel is cut
 // into "super-blocks" of 8x8 tiles (256 x 256 inputs).  A workgroup of four
-// waves takes one tile group:
-//   * a diagonal super-block: a triangle of 36 tiles.  Wave w takes tile
-//     rows w and 7-w (8-w and w+1 tiles), so every wave runs 9 tiles;
+// waves (one per SIMD, 256 accumulator registers each) takes one tile group:
+//   * a diagonal super-block: a triangle of 36 tiles, 8 on the diagonal
+//     and 28 off it.  A diagonal tile costs half (one MFMA chain, 16
+//     accumulator registers).  Waves 0 and 1 take the 2 x 4 rectangles of
+//     tiles (0..1, 4..7) and (2..3, 4..7); waves 2 and 3 take the triangles
+//     of blocks 0..3 and 4..7 (4 diagonal + 6 off-diagonal tiles each);
 //   * half of an off-diagonal super-block: 4 tile rows x 8 tile columns.
-//     Wave w takes rows 2(w/2), 2(w/2)+1 and columns 4(w%2)..+3 (8 tiles).
-// Super-blocks at the edge of the triangle are padded: input blocks past
-// ceil(N/32) are staged as zeros and their tiles are computed but never
-// stored, so every wave has a fixed, compile-time tile pattern.
-// With ns = ceil(blocks / 8) super-rows there are ns diagonal groups and
-// ns(ns-1)/2 off-diagonal super-blocks of two halves each: ns^2 groups.
-// Each workgroup integrates its tiles over one chunk of the frame's time
-// samples; chunks of the same tiles are added into the output.
+//     Wave w takes rows 2(w/2), 2(w/2)+1 and columns 4(w%2)..+3.
+// Every wave thus runs 32 MFMAs per staged step and reads 6 (rectangle)
+// or 8 (triangle) operand fragments per 16 MFMAs.  Super-blocks at the edge
+// of the triangle are padded: input blocks past ceil(N/32) are staged as
+// zeros and their tiles are computed but never stored, so every wave has a
+// fixed, compile-time tile pattern.  With ns = ceil(blocks / 8) super-rows
+// there are ns diagonal groups and ns(ns-1)/2 off-diagonal super-blocks of
+// two halves each: ns^2 groups.  Each workgroup integrates its tiles over
+// one chunk of the frame's time samples; chunks of the same tiles are added
+// into the output.
 #pragma once
 
 #include <stdint.h>
@@ -30,9 +35,12 @@ constexpr int kBlk = 32;          // inputs per tile edge (one 32x32 MFMA)
 constexpr int kStep = 32;         // samples staged per step
 constexpr int kSuper = 8;         // tile blocks per super-block edge
 constexpr int kMaxSlots = 12;     // input blocks staged per workgroup
-constexpr int kTilesPerWave = 9;  // 32x32 accumulator tiles per wave
+constexpr int kTilesPerWave = 10; // (Re, Im) tiles a wave writes out, at most
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
+// |Q| of a diagonal tile grows by at most 248 per sample: a chunk of at
+// most 2^18 steps (8,388,608 samples) keeps it inside int32
+constexpr int kMaxStepsPerChunk = 1 << 18;
 
 // One tile group, in scalars (no arrays: kept in scalar registers on the
 // device).  Slot s of the staged blocks holds input block

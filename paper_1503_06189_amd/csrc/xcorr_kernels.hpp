@@ -7,22 +7,33 @@
 //     Re V_ij = sum_k Xr_i[k] Xr_j[k]      Im V_ij = sum_k Xp_i[k] Xr_j[k]
 //   with Xr = (a, b), Xp = (b, -a): two real int8 GEMMs with K = 2T on the
 //   matrix cores, exact int32 accumulation.  Only tiles with I <= J run.
+//   A diagonal tile (I = J) is Hermitian, so it runs one GEMM:
+//     Q = Xs Xr^T with Xs = Xr + Xp = (a + b, b - a)  (fits int8),
+//     Re = (Q + Q^T) / 2,  Im = (Q - Q^T) / 2  (exact: Q + Q^T = 2 Re).
 //
-// Per staged step of 32 samples a workgroup
-//   1. loads the packed bytes of its input blocks (coalesced dword loads
-//      along the input axis), substitutes 0x88 (= 0) for lost samples and
-//      for samples past the end of its time chunk, transposes 4x4 byte
-//      blocks in registers so each dword holds 4 samples of one input, and
-//      decodes nibbles to signed int8 with carry-free SWAR arithmetic;
-//   2. writes them to LDS in the operand layout of
-//      v_mfma_i32_32x32x32_i8: per block, per 16-sample sub-step, lane l
-//      reads 16 bytes = 8 samples of input (l % 32), (a a a a a a a a
-//      b b b b b b b b); both operands use the same K order, so the order of
-//      samples inside K does not matter for the sum;
-//   3. each wave runs its tiles: the A operand (rows) in Xr and Xp form,
-//      the B operand (columns) in Xr form.
-// At the end each lane adds its accumulators into the packed triangle with
-// integer atomics (exact, any order), which also merges time chunks.
+// A workgroup integrates one tile group (plan.hpp) of one channel over one
+// chunk of time.  Per staged step of 32 samples it
+//   1. loads the packed bytes of its input blocks with dword buffer loads
+//      along the input axis; the buffer range ends at the chunk;
+//   2. substitutes 0x88 (= 0) for lost samples, samples past the chunk and
+//      inputs past N, transposes 4x4 byte blocks in registers so that each
+//      dword holds 4 samples of one input, decodes nibbles to signed int8
+//      with carry-free byte arithmetic and writes LDS in the operand layout
+//      of v_mfma_i32_32x32x32_i8: per block and 16-sample sub-step, lane l
+//      reads 16 bytes = 8 samples of input l % 32.  Both operands use the
+//      same K order, so the order of samples inside K does not change the
+//      sum;
+//   3. runs its tiles: A operand (rows) in Xr, Xp (and Xs) form, B Xr.
+// The loop is software-pipelined: the global loads for step s+2 and the
+// decode of step s+1 into the other LDS buffer overlap the MFMAs of step s;
+// one barrier per step; one wave per SIMD with 256 accumulator registers.
+//
+// Output: a tile group owned by a single workgroup (one time chunk) is
+// written with plain stores (overwrite) or read-add-write (accumulate).
+// When time is split into chunks, every workgroup stores its int32 tiles in
+// the workspace; the last workgroup of a (channel, group) to arrive (device-
+// scope counter) adds all chunks and writes the result.  Integer sums, so
+// the order of chunks does not matter and the result is exact.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,15 +45,26 @@ namespace xe {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
 
-constexpr int kSlotBytes = kBlk * kStep * 2;  // decoded bytes per block per step
-constexpr int kBufBytes = kSlotBytes * kMaxSlots;
+constexpr int kFragBytes = kBlk * kStep * 2;  // one decoded operand of a block per step
+// A diagonal group stages Xr and Xs per block (8 slots x 2 operands), an
+// off-diagonal half stages Xr only (12 slots)
+constexpr int kBufBytes = 16 * kFragBytes;
+// validity bits of a window of steps, one 32-bit word per step
+constexpr int kMaskWindow = 2048;
+// int32 (Re, Im) tiles of one wave in the workspace: 10 tiles x 32 x 64
+constexpr int kWavePartial = kTilesPerWave * 32 * 64;
+constexpr int64_t kGroupPartial = (int64_t)kWaves * kWavePartial;
 
 struct CorrArgs {
     const uint8_t *packed;
     const uint8_t *mask;  // may be null
     int32_t *vis;
     int64_t *count;
+    int32_t *partials;    // [F*groups][splits][kGroupPartial] when splits > 1
+    int32_t *counters;    // [F*groups], zero between launches
     int N, F, T, B;
     int nblk_mask;        // ceil(T / B)
     int nb;               // ceil(N / 32)
@@ -82,246 +104,661 @@ __device__ __forceinline__ void transpose4(const uint32_t d[4], uint32_t out[4])
     out[3] = perm(e3, e1, 0x07060302u);
 }
 
-// Xr fragment (a0..7 | b0..7) -> Xp fragment (b0..7 | -a0..7)
+// 4 validity bits -> 4 byte masks (0xff = valid)
+__device__ __forceinline__ uint32_t bits_to_bytes(uint32_t b4) {
+    uint32_t m = (b4 * 0x00204081u) & 0x01010101u;  // bit k -> byte k
+    return (m << 8) - m;
+}
+
+// A 16-byte operand chunk holds, for 8 samples of one input,
+// (a0..3 | b0..3 | a4..7 | b4..7).  Xr chunk -> Xp chunk (b | -a).
 __device__ __forceinline__ v4i make_xp(v4i x) {
     v4i p;
-    p.x = x.z;
-    p.y = x.w;
-    p.z = (int)neg_s8((uint32_t)x.x);
-    p.w = (int)neg_s8((uint32_t)x.y);
+    p.x = x.y;
+    p.y = (int)neg_s8((uint32_t)x.x);
+    p.z = x.w;
+    p.w = (int)neg_s8((uint32_t)x.z);
     return p;
+}
+
+__device__ __forceinline__ v16i mfma(v4i a, v4i b, v16i c) {
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
+
+// LDS position of the 16-byte chunk c (= lane-group g * 32 + row r) of
+// (block slot s, operand op, sub-step u).  The 64 chunks of one (s, op, u)
+// form 1 KB; lane l of a reading wave takes chunk l, stored at
+//   phys(l, s) = l ^ (s & 1) ^ (bit 4 of l) << 1,
+// a permutation inside aligned groups of 4 chunks, so a wave's 16-byte
+// reads stay conflict-free while the stagers' 8-byte writes (below) hit all
+// 64 banks exactly once per half-wave.
+__device__ __forceinline__ int phys_chunk(int c, int s) {
+    return c ^ (s & 1) ^ (((c >> 4) & 1) << 1);
+}
+__device__ __forceinline__ int chunk_off(int slot_bytes, int s, int op, int u, int c) {
+    return s * slot_bytes + op * kFragBytes + u * 1024 + (phys_chunk(c, s) << 4);
 }
 
 // ---------------------------------------------------------------------------
 // staging: global packed bytes -> decoded int8 operand layout in LDS
 // ---------------------------------------------------------------------------
 
-// 4 consecutive input bytes of one sample; out-of-range or invalid bytes
-// read a safe address and are replaced by 0x88 (= 0), without branches
-template <bool kAligned>
-__device__ __forceinline__ uint32_t load4(const uint8_t *packed, int64_t row_off, int n0,
-                                          int N, bool ok) {
-    if (kAligned) {
-        // N % 4 == 0: the dword is either wholly inside [0, N) or wholly out
-        bool in = ok && n0 < N;
-        const uint32_t *p = (const uint32_t *)(packed + (in ? row_off + n0 : 0));
-        uint32_t v = *p;
-        return in ? v : 0x88888888u;
-    } else {
-        uint32_t v = 0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            bool in = ok && n0 + c < N;
-            uint32_t b = packed[in ? row_off + n0 + c : 0];
-            v |= (in ? b : 0x88u) << (8 * c);
-        }
-        return v;
-    }
+// One staging unit = 4 inputs (n0..n0+3) x 4 samples (sample quad sq of the
+// step) of block slot s.  Units come in rounds of 64 per wave: lane bits
+// (q = lane & 7, s_lo = bit 3, h = bit 4, s_hi = bit 5) give input quad q,
+// slot 4 sg + s_lo + 2 s_hi and sample quad 2 o + h, with the octet o and
+// the slot group sg fixed per wave-round.  Coordinates do not change along
+// the time loop.
+struct Unit {
+    int s, q, sq;
+    uint32_t voff;  // byte offset of (sample 4 sq, input n0) within the chunk;
+                    // out of range (reads 0) when the inputs lie past N
+    bool act;       // inputs lie below N (else staged as 0)
+    uint32_t inb;   // unaligned path: byte c of the dword lies below N
+};
+
+template <int UPT>
+struct Prefetch {
+    uint32_t d[UPT][4];
+};
+
+// The chunk of a workgroup: samples [t_begin, t_end) of channel f, read
+// through a buffer resource whose range ends at the last byte of the chunk,
+// so every load is bounds-checked by the hardware (reads past it return 0;
+// such samples are replaced below anyway).
+struct Chunk {
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t row_bytes;  // F * N: bytes between consecutive samples
+    int t_begin, t_end;
+};
+
+__device__ __forceinline__ Chunk make_chunk(const CorrArgs &a, int f, int t_begin, int t_end) {
+    Chunk c;
+    // every value here is wave-uniform; readfirstlane keeps the resource in
+    // scalar registers (a buffer load needs it there)
+    uint64_t base = (uint64_t)(uintptr_t)(a.packed + ((int64_t)t_begin * a.F + f) * a.N);
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+    uint32_t row = __builtin_amdgcn_readfirstlane((uint32_t)a.F * (uint32_t)a.N);
+    uint32_t extent = __builtin_amdgcn_readfirstlane((uint32_t)(t_end - t_begin - 1) * row +
+                                                     (uint32_t)a.N);
+    void *p = (void *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+    c.rsrc = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)extent, 0x00020000);
+    c.row_bytes = row;
+    c.t_begin = t_begin;
+    c.t_end = t_end;
+    return c;
 }
 
-// validity of samples tb .. tb+31 of channel f within [.., t_end) as a
-// wave-uniform bit mask
-__device__ __forceinline__ uint32_t step_valid_bits(const CorrArgs &a, int f, int tb,
-                                                    int t_end) {
-    int lane = threadIdx.x & 63;
-    int t = tb + (lane & 31);
-    bool ok = lane < 32 && t < t_end;
-    if (ok && a.mask) ok = a.mask[(int64_t)f * a.nblk_mask + t / a.B] == 0;
-    return (uint32_t)__ballot(ok);
-}
-
-// One staging unit: 4 inputs (n0..n0+3) x 8 samples (octet o of the step)
-// of slot s.  Loads 8 dwords, transposes to 4 inputs x 8 samples, decodes
-// and writes four 16-byte operand chunks.
-template <bool kAligned>
-__device__ __forceinline__ void stage_unit(const CorrArgs &a, int f, int tb, uint32_t vbits,
-                                           int s, int q, int o, int n0, bool active,
-                                           uint8_t *buf) {
-    uint32_t d[8];
+template <bool kAligned, int UPT>
+__device__ __forceinline__ void issue_loads(const Chunk &ch, int tb, const Unit (&u)[UPT],
+                                            Prefetch<UPT> &p) {
+    const uint32_t step_off = (uint32_t)(tb - ch.t_begin) * ch.row_bytes;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        int t = tb + 8 * o + e;
-        bool ok = active && ((vbits >> (8 * o + e)) & 1u);
-        int64_t row_off = ((int64_t)t * a.F + f) * a.N;
-        d[e] = load4<kAligned>(a.packed, row_off, n0, a.N, ok);
-    }
-    uint32_t lo[4], hi[4];
-    transpose4(d, lo);
-    transpose4(d + 4, hi);
-    if (active) {
+    for (int r = 0; r < UPT; ++r) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            v4i frag;
-            frag.x = (int)nib_to_s8((lo[c] >> 4) & 0x0f0f0f0fu);
-            frag.y = (int)nib_to_s8((hi[c] >> 4) & 0x0f0f0f0fu);
-            frag.z = (int)nib_to_s8(lo[c] & 0x0f0f0f0fu);
-            frag.w = (int)nib_to_s8(hi[c] & 0x0f0f0f0fu);
-            int r = 4 * q + c;
-            *(v4i *)(buf + s * kSlotBytes + (o * kBlk + r) * 16) = frag;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// the correlation kernel
-// ---------------------------------------------------------------------------
-
-// Main loop of one wave with NA tiles on row slot A and NB on row slot B
-// (compile-time counts, so every accumulator index is static).
-template <bool kAligned, int NA, int NB>
-__device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int f,
-                                         int t_begin, int t_end, int rowA, int colA0,
-                                         int rowB, int colB0, uint8_t *lds) {
-    constexpr int NT = NA + NB;
-    const int lane = threadIdx.x & 63;
-
-    // staging units of this thread (at most two per step)
-    const int units = g.nslots * 32;
-    int us[2], uq[2], uo[2], un0[2];
-    bool uact[2];
+        for (int e = 0; e < 4; ++e) {
+            const int soff = (int)(step_off + (uint32_t)e * ch.row_bytes);
+            if (kAligned) {
+                p.d[r][e] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(ch.rsrc, (int)u[r].voff,
+                                                                           soff, 0);
+            } else {
+                uint32_t v = 0;
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        int u = threadIdx.x + r * kThreads;
-        uact[r] = u < units;
-        uq[r] = u & 7;
-        us[r] = (u >> 3) % g.nslots;
-        uo[r] = (u >> 3) / g.nslots;
-        un0[r] = slot_block(g, us[r]) * kBlk + 4 * uq[r];
-    }
-    const bool two_rounds = units > kThreads;
-
-    v16i acc_re[NT], acc_im[NT];
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        acc_re[k] = (v16i){0};
-        acc_im[k] = (v16i){0};
-    }
-
-    for (int tb = t_begin; tb < t_end; tb += kStep) {
-        uint32_t vbits = step_valid_bits(a, f, tb, t_end);
-        stage_unit<kAligned>(a, f, tb, vbits, us[0], uq[0], uo[0], un0[0], uact[0], lds);
-        if (two_rounds)
-            stage_unit<kAligned>(a, f, tb, vbits, us[1], uq[1], uo[1], un0[1], uact[1], lds);
-        __syncthreads();
-#pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
-            const uint8_t *base = lds + sub * (kBlk * 2 * 16) + lane * 16;
-            v4i xa = *(const v4i *)(base + rowA * kSlotBytes);
-            v4i pa = make_xp(xa);
-            v4i xb = xa, pb = pa;
-            if (NB > 0) {
-                xb = *(const v4i *)(base + rowB * kSlotBytes);
-                pb = make_xp(xb);
+                for (int c = 0; c < 4; ++c) {
+                    uint32_t b = (uint8_t)__builtin_amdgcn_raw_buffer_load_b8(
+                        ch.rsrc, (int)(u[r].voff + c), soff, 0);
+                    v |= (((u[r].inb >> c) & 1u) ? b : 0x88u) << (8 * c);
+                }
+                p.d[r][e] = v;
             }
-#pragma unroll
-            for (int k = 0; k < NT; ++k) {
-                int cs = k < NA ? colA0 + k : colB0 + (k - NA);
-                v4i y = *(const v4i *)(base + cs * kSlotBytes);
-                if (k < NA) {
-                    acc_re[k] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa, y, acc_re[k], 0, 0, 0);
-                    acc_im[k] = __builtin_amdgcn_mfma_i32_32x32x32_i8(pa, y, acc_im[k], 0, 0, 0);
-                } else {
-                    acc_re[k] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xb, y, acc_re[k], 0, 0, 0);
-                    acc_im[k] = __builtin_amdgcn_mfma_i32_32x32x32_i8(pb, y, acc_im[k], 0, 0, 0);
+        }
+    }
+}
+
+// Validity words of steps [s0, s0 + kMaskWindow) of the chunk into LDS: bit k
+// of word s = sample t_begin + 32 s + k lies inside the chunk and not in a
+// lost block.  All threads take part; call between barriers.
+__device__ inline void fill_mask_window(const CorrArgs &a, int f, const Chunk &ch, int s0,
+                                        int nsteps, uint32_t *words) {
+    const uint8_t *m = a.mask ? a.mask + (int64_t)f * a.nblk_mask : nullptr;
+    const int n = (nsteps - s0) < kMaskWindow ? (nsteps - s0) : kMaskWindow;
+    for (int w = threadIdx.x; w < n; w += kThreads) {
+        const int tb = ch.t_begin + (s0 + w) * kStep;
+        const int left = ch.t_end - tb;
+        uint32_t bits = left >= 32 ? 0xffffffffu : ((1u << left) - 1u);
+        if (m) {
+            int blk = tb / a.B;
+            for (int k0 = blk * a.B - tb; k0 < 32 && blk < a.nblk_mask; k0 += a.B, ++blk) {
+                if (m[blk]) {
+                    int lo = k0 < 0 ? 0 : k0;
+                    int hi = k0 + a.B > 32 ? 32 : k0 + a.B;
+                    uint32_t range =
+                        (hi - lo >= 32) ? 0xffffffffu : (((1u << (hi - lo)) - 1u) << lo);
+                    bits &= ~range;
                 }
             }
         }
-        __syncthreads();
+        words[w] = bits;
     }
+}
 
-    // epilogue: add the tiles into the packed upper triangle
-    const int64_t P = (int64_t)a.N * (a.N + 1) / 2;
-    int32_t *visf = a.vis + (int64_t)f * P * 2;
+// Decode one prefetched step into LDS.  Per input, from the masked nibbles
+// A' = a + 8 and B' = b + 8 (4 samples per dword):
+//   Xr = (a | b)             a = (A' + 0x78) ^ 0x80
+//   Xs = (a + b | b - a)     a + b = (A' + B' + 0x70) ^ 0x80,
+//                            b - a = ((B' | 0x80) - A') ^ 0x80
+// all per byte without carries or borrows; Xs only for diagonal groups.
+// A unit writes bytes 8h .. 8h+7 of its inputs' chunks (h = sq & 1).
+template <bool kXs, int UPT>
+__device__ __forceinline__ void commit(const Unit (&u)[UPT], const Prefetch<UPT> &p,
+                                       uint32_t vbits, uint8_t *buf, int slot_bytes) {
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        int rs = k < NA ? rowA : rowB;
-        int cs = k < NA ? colA0 + k : colB0 + (k - NA);
-        int I = slot_block(g, rs), J = slot_block(g, cs);
-        int j = J * kBlk + (lane & 31);
+    for (int r = 0; r < UPT; ++r) {
+        uint32_t L[4];
+        transpose4(p.d[r], L);
+        const uint32_t vq = u[r].act ? (vbits >> (4 * u[r].sq)) & 15u : 0u;
+        const uint32_t m = bits_to_bytes(vq);
+        const int o = u[r].sq >> 1, h = u[r].sq & 1;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            int i = I * kBlk + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-            if (i <= j && j < a.N) {
-                int64_t idx = (int64_t)i * a.N - (int64_t)i * (i - 1) / 2 + (j - i);
-                atomicAdd(&visf[2 * idx], acc_re[k][v]);
-                atomicAdd(&visf[2 * idx + 1], acc_im[k][v]);
+        for (int c = 0; c < 4; ++c) {
+            uint32_t Lm = (L[c] & m) | (0x88888888u & ~m);
+            uint32_t an = (Lm >> 4) & 0x0f0f0f0fu, bn = Lm & 0x0f0f0f0fu;
+            uint8_t *dst = buf + chunk_off(slot_bytes, u[r].s, 0, o >> 1,
+                                           (o & 1) * 32 + 4 * u[r].q + c) + 8 * h;
+            v2u xr = {nib_to_s8(an), nib_to_s8(bn)};
+            *(v2u *)dst = xr;
+            if (kXs) {
+                v2u xs = {(an + bn + 0x70707070u) ^ 0x80808080u,
+                          ((bn | 0x80808080u) - an) ^ 0x80808080u};
+                *(v2u *)(dst + kFragBytes) = xs;
             }
         }
     }
 }
 
-template <bool kAligned>
-__global__ __launch_bounds__(kThreads, 1) void corr_kernel(CorrArgs a) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[kBufBytes];
+// ---------------------------------------------------------------------------
+// the tiles of one wave
+// ---------------------------------------------------------------------------
 
-    const int G = a.groups;
-    int64_t wg = blockIdx.x;
-    const int gid = (int)(wg % G);
-    wg /= G;
-    const int split = (int)(wg % a.splits);
-    const int f = (int)(wg / a.splits);
+// Two tile shapes (see plan.hpp):
+//   kRect: rows s0, s0+1 x columns c0 .. c0+3 (8 off-diagonal tiles);
+//   kTri:  the triangle of blocks s0 .. s0+3: 4 diagonal tiles (as Q) and
+//          the 6 pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3).
+enum Shape { kRect = 0, kTri = 1 };
 
-    const Group g = make_group(a.nb, gid);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+template <int SHAPE>
+struct Tiles;
+
+template <>
+struct Tiles<kRect> {
+    static constexpr int NQ = 0, NO = 8, NT = 8;
+    __device__ static constexpr int row(int k) { return k / 4; }      // of the off tiles
+    __device__ static constexpr int col(int k) { return k % 4; }
+};
+
+template <>
+struct Tiles<kTri> {
+    static constexpr int NQ = 4, NO = 6, NT = 10;
+    __device__ static constexpr int row(int k) { return k < 3 ? 0 : (k < 5 ? 1 : 2); }
+    __device__ static constexpr int col(int k) { return k < 3 ? k + 1 : (k < 5 ? k - 1 : 3); }
+};
+
+template <int SHAPE>
+struct Acc {
+    using T = Tiles<SHAPE>;
+    v16i q[T::NQ > 0 ? T::NQ : 1];
+    v16i re[T::NO], im[T::NO];
+};
+
+// MFMAs of one staged step.  Both sub-steps' operands are read first.
+template <int SHAPE>
+__device__ __forceinline__ void compute_step(const uint8_t *buf, int slot_bytes, int s0, int c0,
+                                             Acc<SHAPE> &acc) {
+    const int lane = threadIdx.x & 63;
+    auto frag = [&](int s, int op, int sub) {
+        return *(const v4i *)(buf + chunk_off(slot_bytes, s, op, sub, lane));
+    };
+    if (SHAPE == kRect) {
+        v4i x[2][2], y[2][4];
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) x[sub][i] = frag(s0 + i, 0, sub);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) y[sub][j] = frag(c0 + j, 0, sub);
+        }
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                v4i p = make_xp(x[sub][i]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc.re[4 * i + j] = mfma(x[sub][i], y[sub][j], acc.re[4 * i + j]);
+                    acc.im[4 * i + j] = mfma(p, y[sub][j], acc.im[4 * i + j]);
+                }
+            }
+        }
+    } else {
+        v4i x[2][4], xs[2][4];
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                x[sub][i] = frag(s0 + i, 0, sub);
+                xs[sub][i] = frag(s0 + i, 1, sub);
+            }
+        }
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc.q[i] = mfma(xs[sub][i], x[sub][i], acc.q[i]);
+            v4i p[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) p[i] = make_xp(x[sub][i]);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const int i = Tiles<kTri>::row(k), j = Tiles<kTri>::col(k);
+                acc.re[k] = mfma(x[sub][i], x[sub][j], acc.re[k]);
+                acc.im[k] = mfma(p[i], x[sub][j], acc.im[k]);
+            }
+        }
+    }
+}
+
+// One loop step with the decode of the next step woven into the MFMA
+// stream.  The wave is alone on its SIMD, so it must itself keep the matrix
+// core busy while it decodes: the 32 MFMAs are issued in a fixed order and
+// after every few of them comes one small piece of the decode (a 4x4
+// transpose, or the decode and LDS write of one input), pinned in place by
+// scheduling barriers.  A piece's VALU work issues while the MFMA before it
+// occupies the matrix core.
+template <int SHAPE, bool kXs, int UPT>
+__device__ __forceinline__ void fused_step(const uint8_t *cur, uint8_t *nxt, int slot_bytes,
+                                           int s0, int c0, Acc<SHAPE> &acc,
+                                           const Unit (&u)[UPT], const Prefetch<UPT> &p,
+                                           uint32_t vbits) {
+    constexpr int kPieces = 5 * UPT;  // per unit: transpose, 4 inputs
+    const int lane = threadIdx.x & 63;
+    auto frag = [&](int s, int op, int sub) {
+        return *(const v4i *)(cur + chunk_off(slot_bytes, s, op, sub, lane));
+    };
+    constexpr int NX = SHAPE == kRect ? 2 : 4;   // row operands
+    constexpr int NY = SHAPE == kRect ? 4 : 0;   // column operands (rectangles)
+    v4i x[2][NX], y[2][NY > 0 ? NY : 1], xs[2][SHAPE == kTri ? 4 : 1], xp[NX];
+    auto read_sub = [&](int sub) {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            x[sub][i] = frag(s0 + i, 0, sub);
+            if (SHAPE == kTri) xs[sub][i] = frag(s0 + i, 1, sub);
+        }
+#pragma unroll
+        for (int j = 0; j < NY; ++j) y[sub][j] = frag(c0 + j, 0, sub);
+    };
+    // decode state
+    uint32_t L[UPT][4];
+    uint32_t msk[UPT];
+    auto piece = [&](int k) {
+        const int r = k / 5, c = k % 5 - 1;
+        if (c < 0) {
+            transpose4(p.d[r], L[r]);
+            const uint32_t vq = u[r].act ? (vbits >> (4 * u[r].sq)) & 15u : 0u;
+            msk[r] = bits_to_bytes(vq);
+        } else {
+            const int o = u[r].sq >> 1, h = u[r].sq & 1;
+            uint32_t Lm = (L[r][c] & msk[r]) | (0x88888888u & ~msk[r]);
+            uint32_t an = (Lm >> 4) & 0x0f0f0f0fu, bn = Lm & 0x0f0f0f0fu;
+            uint8_t *dst = nxt + chunk_off(slot_bytes, u[r].s, 0, o >> 1,
+                                           (o & 1) * 32 + 4 * u[r].q + c) + 8 * h;
+            v2u xr = {nib_to_s8(an), nib_to_s8(bn)};
+            *(v2u *)dst = xr;
+            if (kXs) {
+                v2u v = {(an + bn + 0x70707070u) ^ 0x80808080u,
+                         ((bn | 0x80808080u) - an) ^ 0x80808080u};
+                *(v2u *)(dst + kFragBytes) = v;
+            }
+        }
+    };
+    // MFMA m of the step (m = 16 sub + op)
+    auto mfma_op = [&](int m) {
+        const int sub = m / 16, k = m % 16;
+        if (SHAPE == kRect) {
+            const int t = k / 2, i = t / 4, j = t % 4;
+            if (k % 2 == 0)
+                acc.re[t] = mfma(x[sub][i], y[sub][j], acc.re[t]);
+            else
+                acc.im[t] = mfma(xp[i], y[sub][j], acc.im[t]);
+        } else {
+            if (k < 4) {
+                acc.q[k] = mfma(xs[sub][k], x[sub][k], acc.q[k]);
+            } else {
+                const int t = (k - 4) / 2;
+                const int i = Tiles<kTri>::row(t), j = Tiles<kTri>::col(t);
+                if (k % 2 == 0)
+                    acc.re[t] = mfma(x[sub][i], x[sub][j], acc.re[t]);
+                else
+                    acc.im[t] = mfma(xp[i], x[sub][j], acc.im[t]);
+            }
+        }
+    };
+
+    read_sub(0);
+    read_sub(1);
+#pragma unroll
+    for (int m = 0; m < 32; ++m) {
+        if (m % 16 == 0) {
+#pragma unroll
+            for (int i = 0; i < NX; ++i) xp[i] = make_xp(x[m / 16][i]);
+        }
+        mfma_op(m);
+        // pieces spread evenly over the 32 MFMAs
+        constexpr int kStride = 32 / kPieces > 0 ? 32 / kPieces : 1;
+        if (m % kStride == kStride - 1 && m / kStride < kPieces) piece(m / kStride);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int k = 32 / (32 / kPieces > 0 ? 32 / kPieces : 1); k < kPieces; ++k) piece(k);
+}
+
+// valid samples of channel f in [t0, t1)
+__device__ inline int64_t valid_count(const CorrArgs &a, int f, int t0, int t1) {
+    if (a.mask == nullptr) return t1 - t0;
+    int64_t n = 0;
+    for (int b = t0 / a.B; (int64_t)b * a.B < t1; ++b) {
+        int64_t lo = (int64_t)b * a.B, hi = lo + a.B;
+        if (lo < t0) lo = t0;
+        if (hi > t1) hi = t1;
+        if (a.mask[(int64_t)f * a.nblk_mask + b] == 0) n += hi - lo;
+    }
+    return n;
+}
+
+// Q of a diagonal tile -> (Re, Im) = ((Q + Q^T) / 2, (Q - Q^T) / 2), exact
+// (Q + Q^T = 2 Re is even; int64 so the sum cannot wrap).  The transpose
+// goes through LDS (32 x 33 int32 per wave, padded against bank conflicts).
+__device__ __forceinline__ void split_q(const v16i &q, int32_t *tbuf, v16i &re, v16i &im) {
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 31;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        tbuf[row * 33 + col] = q[v];
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS writes landed
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        int64_t qij = q[v], qji = tbuf[col * 33 + row];
+        re[v] = (int32_t)((qij + qji) >> 1);
+        im[v] = (int32_t)((qij - qji) >> 1);
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <bool kAligned, bool kOverwrite, int NSLOT, int SHAPE>
+__device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int f, int gid,
+                                         int split, int s0, int c0, uint8_t *lds,
+                                         uint32_t *mwords, int *s_flag) {
+    using TL = Tiles<SHAPE>;
+    constexpr int UPT = NSLOT / 4;     // wave-rounds of 64 units per wave
+    constexpr bool kDiagGroup = NSLOT == 8;
+    constexpr int SLOT = kDiagGroup ? 2 * kFragBytes : kFragBytes;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
 
     const int t_begin = split * a.steps_per_split * kStep;
     int t_end = t_begin + a.steps_per_split * kStep;
     if (t_end > a.T) t_end = a.T;
+    const int nsteps = (t_end - t_begin + kStep - 1) / kStep;
+
+    const Chunk ch = make_chunk(a, f, t_begin, t_end);
+    Unit u[UPT];
+#pragma unroll
+    for (int r = 0; r < UPT; ++r) {
+        const int x = r * kWaves + wave;  // wave-round: 64 units
+        const int o = x / (NSLOT / 4), sg = x % (NSLOT / 4);
+        const int h = (lane >> 4) & 1;
+        u[r].q = lane & 7;
+        u[r].s = 4 * sg + ((lane >> 3) & 1) + 2 * ((lane >> 5) & 1);
+        u[r].sq = 2 * o + h;
+        int n0 = slot_block(g, u[r].s) * kBlk + 4 * u[r].q;
+        u[r].act = n0 < a.N;
+        u[r].voff = u[r].act ? (uint32_t)(4 * u[r].sq) * ch.row_bytes + (uint32_t)n0
+                             : 0x80000000u;
+        u[r].inb = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) u[r].inb |= (n0 + c < a.N ? 1u : 0u) << c;
+    }
+
+    Acc<SHAPE> acc;
+#pragma unroll
+    for (int k = 0; k < TL::NO; ++k) {
+        acc.re[k] = (v16i){0};
+        acc.im[k] = (v16i){0};
+    }
+#pragma unroll
+    for (int k = 0; k < TL::NQ; ++k) acc.q[k] = (v16i){0};
+
+    // pipeline: loads run two steps ahead, decode one step ahead
+    fill_mask_window(a, f, ch, 0, nsteps, mwords);
+    Prefetch<UPT> p_next, p_far;
+    issue_loads<kAligned>(ch, t_begin, u, p_next);
+    __syncthreads();
+    commit<kDiagGroup>(u, p_next, __builtin_amdgcn_readfirstlane(mwords[0]), lds, SLOT);
+    issue_loads<kAligned>(ch, t_begin + kStep, u, p_next);
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+        uint8_t *cur = lds + (s & 1) * kBufBytes;
+        uint8_t *nxt = lds + ((s + 1) & 1) * kBufBytes;
+        if ((s + 1) % kMaskWindow == 0 && s + 1 < nsteps) {
+            // next window of validity words (uniform branch, rare)
+            fill_mask_window(a, f, ch, s + 1, nsteps, mwords);
+            __syncthreads();
+        }
+        const uint32_t vbits =
+            s + 1 < nsteps ? __builtin_amdgcn_readfirstlane(mwords[(s + 1) % kMaskWindow]) : 0u;
+        issue_loads<kAligned>(ch, t_begin + (s + 2) * kStep, u, p_far);
+        fused_step<SHAPE, kDiagGroup>(cur, nxt, SLOT, s0, c0, acc, u, p_next, vbits);
+        __syncthreads();
+        p_next = p_far;
+    }
+
+    // ---- epilogue, one tile at a time -----------------------------------
+    // tiles of this wave: k < NQ diagonal, then the off-diagonal ones
+    constexpr int NT = TL::NT;
+    int32_t *tbuf = (int32_t *)lds + wave * (32 * 33);  // staging buffers are free now
+    const int64_t key = (int64_t)f * a.groups + gid;
+    const int64_t P = (int64_t)a.N * (a.N + 1) / 2;
+    int32_t *visf = a.vis + (int64_t)f * P * 2;
+
+    auto tile_rc = [&](int k, int &rs, int &cs) {
+        if (k < TL::NQ) {
+            rs = cs = s0 + k;
+        } else if (SHAPE == kRect) {
+            rs = s0 + TL::row(k - TL::NQ);
+            cs = c0 + TL::col(k - TL::NQ);
+        } else {
+            rs = s0 + TL::row(k - TL::NQ);
+            cs = s0 + TL::col(k - TL::NQ);
+        }
+    };
+    auto tile = [&](int k, v16i &re, v16i &im) {
+        if (k < TL::NQ) {
+            split_q(acc.q[k < TL::NQ ? k : 0], tbuf, re, im);
+        } else {
+            re = acc.re[k - TL::NQ];
+            im = acc.im[k - TL::NQ];
+        }
+    };
+    // element v of tile k held by this lane: its index in the packed
+    // triangle, or -1 when it lies below the diagonal or past N
+    auto elem = [&](int k, int v) -> int64_t {
+        int rs, cs;
+        tile_rc(k, rs, cs);
+        int i = slot_block(g, rs) * kBlk + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        int j = slot_block(g, cs) * kBlk + (lane & 31);
+        if (i > j || j >= a.N) return -1;
+        return (int64_t)i * a.N - (int64_t)i * (i - 1) / 2 + (j - i);
+    };
+    // previous contents of tile k (accumulate mode), all loads issued
+    // before any store of the tile so they overlap
+    auto load_old = [&](int k, v2i (&old)[16]) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            int64_t idx = elem(k, v);
+            old[v] = idx >= 0 ? *(const v2i *)(visf + 2 * idx) : (v2i){0, 0};
+        }
+    };
+    auto store = [&](int k, const v16i &re, const v16i &im, const v2i (&old)[16]) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            int64_t idx = elem(k, v);
+            if (idx >= 0) {
+                v2i val = {re[v], im[v]};
+                *(v2i *)(visf + 2 * idx) = kOverwrite ? val : old[v] + val;
+            }
+        }
+    };
+    // partial layout per wave: [tile k][re 0..3 | im 4..7][lane] x 4 int32
+    auto part = [&](int sp) {
+        return a.partials + (key * a.splits + sp) * kGroupPartial + (int64_t)wave * kWavePartial;
+    };
+
+    v2i old[16];
+    if (a.splits == 1) {
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (!kOverwrite) load_old(k, old);
+            v16i re, im;
+            tile(k, re, im);
+            store(k, re, im, old);
+        }
+    } else {
+        // merge time chunks: everyone writes its tiles; the last to arrive
+        // sums all of them
+        int32_t *mine = part(split);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            v16i re, im;
+            tile(k, re, im);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                v4i x = {re[4 * v], re[4 * v + 1], re[4 * v + 2], re[4 * v + 3]};
+                v4i y = {im[4 * v], im[4 * v + 1], im[4 * v + 2], im[4 * v + 3]};
+                *(v4i *)(mine + ((k * 8 + v) * 64 + lane) * 4) = x;
+                *(v4i *)(mine + ((k * 8 + 4 + v) * 64 + lane) * 4) = y;
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int old_count = atomicAdd(&a.counters[key], 1);
+            *s_flag = (old_count == a.splits - 1);
+        }
+        __syncthreads();
+        if (!*s_flag) return;
+        __threadfence();
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (!kOverwrite) load_old(k, old);
+            v16i re = (v16i){0}, im = (v16i){0};
+            for (int sp = 0; sp < a.splits; ++sp) {
+                const int32_t *src = part(sp);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    v4i x = *(const v4i *)(src + ((k * 8 + v) * 64 + lane) * 4);
+                    v4i y = *(const v4i *)(src + ((k * 8 + 4 + v) * 64 + lane) * 4);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        re[4 * v + c] += x[c];
+                        im[4 * v + c] += y[c];
+                    }
+                }
+            }
+            store(k, re, im, old);
+        }
+        if (threadIdx.x == 0) a.counters[key] = 0;  // ready for the next launch
+    }
+    if (gid == 0 && threadIdx.x == 0) {
+        int64_t n = valid_count(a, f, 0, a.T);
+        a.count[f] = kOverwrite ? n : a.count[f] + n;
+    }
+}
+
+// Workgroup b runs on XCD b % 8 (round-robin dispatch); number the work so
+// that consecutive work items (the time chunks and groups of one channel)
+// share an XCD and its L2.
+__device__ __forceinline__ int64_t xcd_local_index(int64_t b, int64_t total) {
+    const int64_t per = total / 8, rem = total % 8;
+    const int64_t x = b % 8, idx = b / 8;
+    return x * per + (x < rem ? x : rem) + idx;
+}
+
+template <bool kAligned, bool kOverwrite>
+__global__ __launch_bounds__(kThreads, 1) void corr_kernel(CorrArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
+    __shared__ uint32_t mwords[kMaskWindow];
+    __shared__ int s_flag;
+
+    const int G = a.groups;
+    const int64_t total = (int64_t)a.F * G * a.splits;
+    int64_t w = xcd_local_index(blockIdx.x, total);
+    const int gid = (int)(w % G);
+    w /= G;
+    const int split = (int)(w % a.splits);
+    const int f = (int)(w / a.splits);
+
+    const Group g = make_group(a.nb, gid);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
     // Every wave runs the same number of steps and barriers; the tile
     // pattern is fixed per group kind (blocks past N are staged as zeros).
     if (g.diag) {
-        // rows w and 7-w of the 8-block triangle
-        const int rA = wave, rB = 7 - wave;
-        switch (wave) {
-            case 0: run_wave<kAligned, 8, 1>(a, g, f, t_begin, t_end, rA, rA, rB, rB, lds); break;
-            case 1: run_wave<kAligned, 7, 2>(a, g, f, t_begin, t_end, rA, rA, rB, rB, lds); break;
-            case 2: run_wave<kAligned, 6, 3>(a, g, f, t_begin, t_end, rA, rA, rB, rB, lds); break;
-            default: run_wave<kAligned, 5, 4>(a, g, f, t_begin, t_end, rA, rA, rB, rB, lds); break;
-        }
+        if (wave < 2)  // rows 2w, 2w+1 x columns 4..7
+            run_wave<kAligned, kOverwrite, 8, kRect>(a, g, f, gid, split, 2 * wave, 4, lds,
+                                                     mwords, &s_flag);
+        else           // triangle of blocks 4(w-2) .. 4(w-2)+3
+            run_wave<kAligned, kOverwrite, 8, kTri>(a, g, f, gid, split, 4 * (wave - 2), 0, lds,
+                                                    mwords, &s_flag);
     } else {
         // rows 2(w/2), 2(w/2)+1 x column slots 4 + 4(w%2) .. +3
-        const int rA = 2 * (wave / 2), c0 = 4 + 4 * (wave % 2);
-        run_wave<kAligned, 4, 4>(a, g, f, t_begin, t_end, rA, c0, rA + 1, c0, lds);
-    }
-
-    // valid samples of this chunk, once per (channel, chunk)
-    if (gid == 0 && threadIdx.x == 0) {
-        int64_t n = 0;
-        if (a.mask == nullptr) {
-            n = t_end - t_begin;
-        } else {
-            for (int b = t_begin / a.B; b * (int64_t)a.B < t_end; ++b) {
-                int64_t lo = (int64_t)b * a.B, hi = lo + a.B;
-                if (lo < t_begin) lo = t_begin;
-                if (hi > t_end) hi = t_end;
-                if (a.mask[(int64_t)f * a.nblk_mask + b] == 0) n += hi - lo;
-            }
-        }
-        atomicAdd((unsigned long long *)&a.count[f], (unsigned long long)n);
+        run_wave<kAligned, kOverwrite, 12, kRect>(a, g, f, gid, split, 2 * (wave / 2),
+                                                  4 + 4 * (wave % 2), lds, mwords, &s_flag);
     }
 }
 
 // ---------------------------------------------------------------------------
-// small kernels
+// normalisation
 // ---------------------------------------------------------------------------
 
-__global__ void zero_kernel(int32_t *vis, int64_t n_vis, int64_t *count, int F) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_vis; k += stride)
-        vis[k] = 0;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < F; k += stride)
-        count[k] = 0;
-}
-
-// out = (float)((double)v / (double)n), 0 when n == 0
+// out = (float)((double)v / (double)n), 0 when n == 0; four values per
+// thread and iteration (16-byte accesses when kVec: both pointers aligned)
+template <bool kVec>
 __global__ void normalize_kernel(const int32_t *vis, const int64_t *count, float *out,
                                  int64_t per_channel, int F) {
-    int64_t total = per_channel * F;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total; k += stride) {
-        int64_t n = count[k / per_channel];
-        out[k] = n == 0 ? 0.0f : (float)((double)vis[k] / (double)n);
+    const int64_t total = per_channel * F;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+    for (int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * 4; k < total;
+         k += stride) {
+        if (kVec && k + 4 <= total && (k / per_channel) == ((k + 3) / per_channel)) {
+            int64_t n = count[k / per_channel];
+            v4i v = *(const v4i *)(vis + k);
+            double dn = (double)n;
+            float4 o;
+            o.x = n == 0 ? 0.0f : (float)((double)v.x / dn);
+            o.y = n == 0 ? 0.0f : (float)((double)v.y / dn);
+            o.z = n == 0 ? 0.0f : (float)((double)v.z / dn);
+            o.w = n == 0 ? 0.0f : (float)((double)v.w / dn);
+            *(float4 *)(out + k) = o;
+        } else {
+            for (int64_t e = k; e < k + 4 && e < total; ++e) {
+                int64_t n = count[e / per_channel];
+                out[e] = n == 0 ? 0.0f : (float)((double)vis[e] / (double)n);
+            }
+        }
     }
 }
 

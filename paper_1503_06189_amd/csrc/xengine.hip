@@ -47,7 +47,7 @@ struct DeviceGuard {
     }
     ~DeviceGuard() {
         int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
     }
 };
 
@@ -62,6 +62,9 @@ xe_status check_shape(xe_handle h, int32_t N, int32_t F, int32_t T, int32_t B) {
     int64_t P = (int64_t)N * (N + 1) / 2;
     if ((int64_t)F * P * 2 > ((int64_t)1 << 40)) return fail(h, XE_ERR_ARG, "F*P too large");
     if ((int64_t)T * F * N > ((int64_t)1 << 40)) return fail(h, XE_ERR_ARG, "frame too large");
+    // a staged step of 32 samples must stay addressable with 32-bit offsets
+    if ((int64_t)F * N * xe::kStep >= ((int64_t)1 << 30))
+        return fail(h, XE_ERR_ARG, "F*N too large for one call");
     return XE_OK;
 }
 
@@ -75,30 +78,64 @@ xe_status check_frame(xe_handle h, const uint8_t *packed, int32_t N, int32_t F, 
     return XE_OK;
 }
 
-void fill_plan(int32_t N, int32_t F, int32_t T, int32_t n_cu, xe_plan_info *p) {
+// Workspace layout: [counters: kCounterBytes][partial accumulators ...]
+constexpr size_t kCounterBytes = 1u << 20;
+constexpr int64_t kMaxKeys = kCounterBytes / sizeof(int32_t);
+
+size_t partial_bytes(int64_t keys, int splits) {
+    return splits > 1 ? (size_t)keys * splits * xe::kGroupPartial * sizeof(int32_t) : 0;
+}
+
+// Returns false when time chunks are unavoidable but their partial sums do
+// not fit the workspace.
+bool fill_plan(int32_t N, int32_t F, int32_t T, int32_t n_cu, size_t ws_bytes,
+               xe_plan_info *p) {
     int nb = xe::ceil_div(N, xe::kBlk);
     int G = xe::groups_per_channel(nb);
     int steps = xe::ceil_div(T, xe::kStep);
     int splits, sps;
-    xe::choose_split((int64_t)F * G, steps, n_cu, &splits, &sps);
+    int64_t keys = (int64_t)F * G;
+    xe::choose_split(keys, steps, n_cu, &splits, &sps);
+    // Chunk limits: the byte offsets inside a chunk stay below 2^31, and a
+    // diagonal tile's Q (at most 248 per sample) stays within int32.
+    const int64_t step_bytes = (int64_t)F * N * xe::kStep;
+    int64_t max_sps = (((int64_t)1 << 31) - 1) / step_bytes - 1;
+    if (max_sps > xe::kMaxStepsPerChunk) max_sps = xe::kMaxStepsPerChunk;
+    if (sps > max_sps) {
+        sps = (int)max_sps;
+        splits = xe::ceil_div(steps, sps);
+    }
+    // fewer chunks when their partial sums do not fit the workspace
+    while (splits > 1 && (keys > kMaxKeys || kCounterBytes + partial_bytes(keys, splits) > ws_bytes)) {
+        int want = splits - 1;
+        int next = xe::ceil_div(steps, want);
+        if (next > max_sps) break;  // cannot merge chunks any further
+        sps = next;
+        splits = xe::ceil_div(steps, sps);
+    }
     p->blocks = nb;
     p->groups = G;
     p->splits = splits;
     p->steps_per_split = sps;
-    p->workgroups = (int64_t)F * G * splits;
+    p->workgroups = keys * splits;
     p->mfma_tiles = xe::tiles_per_channel(nb);
+    return splits == 1 ||
+           (keys <= kMaxKeys && kCounterBytes + partial_bytes(keys, splits) <= ws_bytes);
 }
 
 xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, int32_t N,
                       int32_t F, int32_t T, int32_t B, int32_t *vis, int64_t *count,
-                      hipStream_t stream) {
+                      bool overwrite, hipStream_t stream) {
     xe_plan_info p;
-    fill_plan(N, F, T, h->n_cu, &p);
+    if (!fill_plan(N, F, T, h->n_cu, h->workspace_bytes, &p))
+        return fail(h, XE_ERR_WORKSPACE, "time chunks do not fit the workspace");
     xe::CorrArgs a;
     a.packed = packed;
     a.mask = mask;
     a.vis = vis;
     a.count = count;
+    a.counters = (int32_t *)h->workspace;
+    a.partials = (int32_t *)((char *)h->workspace + kCounterBytes);
     a.N = N;
     a.F = F;
     a.T = T;
@@ -111,10 +148,14 @@ xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, i
     if (p.workgroups > 0x7fffffff) return fail(h, XE_ERR_ARG, "too many workgroups");
     dim3 grid((unsigned)p.workgroups), block(xe::kThreads);
     bool al = aligned(packed, 4) && (N % 4 == 0);
-    if (al)
-        hipLaunchKernelGGL(xe::corr_kernel<true>, grid, block, 0, stream, a);
+    if (al && overwrite)
+        hipLaunchKernelGGL((xe::corr_kernel<true, true>), grid, block, 0, stream, a);
+    else if (al)
+        hipLaunchKernelGGL((xe::corr_kernel<true, false>), grid, block, 0, stream, a);
+    else if (overwrite)
+        hipLaunchKernelGGL((xe::corr_kernel<false, true>), grid, block, 0, stream, a);
     else
-        hipLaunchKernelGGL(xe::corr_kernel<false>, grid, block, 0, stream, a);
+        hipLaunchKernelGGL((xe::corr_kernel<false, false>), grid, block, 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "correlation launch");
     return XE_OK;
@@ -154,7 +195,8 @@ xe_status xe_create(xe_handle *out, int32_t hip_device, size_t workspace_bytes) 
         return XE_ERR_UNSUPPORTED;
     }
     h->n_cu = prop.multiProcessorCount;
-    if (workspace_bytes == 0) workspace_bytes = 4u << 20;
+    if (workspace_bytes == 0) workspace_bytes = (size_t)256 << 20;
+    if (workspace_bytes < kCounterBytes) workspace_bytes = kCounterBytes;
     {
         DeviceGuard g(hip_device);
         if (!g.ok) {
@@ -163,6 +205,14 @@ xe_status xe_create(xe_handle *out, int32_t hip_device, size_t workspace_bytes) 
         }
         e = hipMalloc(&h->workspace, workspace_bytes);
         if (e != hipSuccess) {
+            delete h;
+            return XE_ERR_HIP;
+        }
+        // arrival counters start at zero; every launch leaves them at zero
+        e = hipMemset(h->workspace, 0, kCounterBytes);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            (void)hipFree(h->workspace);
             delete h;
             return XE_ERR_HIP;
         }
@@ -176,7 +226,7 @@ xe_status xe_destroy(xe_handle h) {
     if (!h) return XE_OK;
     if (h->workspace) {
         DeviceGuard g(h->device);
-        hipFree(h->workspace);
+        (void)hipFree(h->workspace);
     }
     delete h;
     return XE_OK;
@@ -204,7 +254,7 @@ xe_status xe_plan_query(int32_t N, int32_t F, int32_t T, int32_t B, int32_t n_cu
     xe_status s = check_shape(nullptr, N, F, T, B);
     if (s != XE_OK) return s;
     if (n_cu < 1) return XE_ERR_ARG;
-    fill_plan(N, F, T, n_cu, info);
+    if (!fill_plan(N, F, T, n_cu, (size_t)256 << 20, info)) return XE_ERR_WORKSPACE;
     return XE_OK;
 }
 
@@ -216,7 +266,8 @@ xe_status xe_accumulate(xe_handle h, const uint8_t *packed, const uint8_t *loss_
     if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
-    return launch_corr(h, packed, loss_mask, N, F, T, B, vis, count, (hipStream_t)stream);
+    return launch_corr(h, packed, loss_mask, N, F, T, B, vis, count, false,
+                       (hipStream_t)stream);
 }
 
 xe_status xe_correlate_frame(xe_handle h, const uint8_t *packed, const uint8_t *loss_mask,
@@ -227,12 +278,8 @@ xe_status xe_correlate_frame(xe_handle h, const uint8_t *packed, const uint8_t *
     if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
-    int64_t n_vis = (int64_t)F * N * (N + 1);
-    hipLaunchKernelGGL(xe::zero_kernel, dim3(1024), dim3(256), 0, (hipStream_t)stream, vis,
-                       n_vis, count, F);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(h, e, "zero launch");
-    return launch_corr(h, packed, loss_mask, N, F, T, B, vis, count, (hipStream_t)stream);
+    return launch_corr(h, packed, loss_mask, N, F, T, B, vis, count, true,
+                       (hipStream_t)stream);
 }
 
 xe_status xe_normalize(xe_handle h, const int32_t *vis, const int64_t *count, int32_t N,
@@ -253,8 +300,12 @@ xe_status xe_normalize(xe_handle h, const int32_t *vis, const int64_t *count, in
     int64_t total = per * F;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(xe::normalize_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                       (hipStream_t)stream, vis, count, out, per, F);
+    if (aligned(vis, 16) && aligned(out, 16))
+        hipLaunchKernelGGL(xe::normalize_kernel<true>, dim3((unsigned)blocks), dim3(256), 0,
+                           (hipStream_t)stream, vis, count, out, per, F);
+    else
+        hipLaunchKernelGGL(xe::normalize_kernel<false>, dim3((unsigned)blocks), dim3(256), 0,
+                           (hipStream_t)stream, vis, count, out, per, F);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "normalize launch");
     return XE_OK;

@@ -113,19 +113,28 @@ def test_plan_query_shapes():
 
 
 def test_tile_groups_cover_the_triangle_once():
-    """Host model of the tile decomposition: every (I <= J) block pair of
-    the triangle is owned by exactly one (group, wave, tile) for many N."""
+    """Host model of the tile decomposition (eight waves per group): every
+    (I <= J) block pair of the triangle is owned by exactly one tile of one
+    wave of one group, for many N, and every wave has 16 MFMAs per step."""
     def groups(nb):
         ns = -(-nb // 8)
         out = []
         for gid in range(ns * ns):
             if gid < ns:
-                base = 8 * gid
-                slots = [base + s for s in range(8)]
-                for w in range(4):
-                    for (r, n) in ((w, 8 - w), (7 - w, w + 1)):
-                        for k in range(n):
-                            out.append((slots[r], slots[r + k]))
+                slots = [8 * gid + s for s in range(8)]
+                for w in range(8):
+                    tiles, mfmas = [], 0
+                    if w < 4:
+                        tiles += [(w, w + 1 + k) for k in range(4)]
+                        mfmas = 2 * 4
+                    else:
+                        p = w - 4
+                        tiles += [(p, p), (7 - p, 7 - p)]
+                        tiles += [(p, p + 5 + k) for k in range(3 - p)]
+                        tiles += [(7 - p, 8 - p + k) for k in range(p)]
+                        mfmas = 2 + 2 * 3
+                    assert mfmas == 8 and len(set(tiles)) == len(tiles)
+                    out += [(slots[r], slots[c]) for r, c in tiles]
             else:
                 q = gid - ns
                 p, half = q // 2, q % 2
@@ -135,14 +144,13 @@ def test_tile_groups_cover_the_triangle_once():
                     R += 1
                 C = R + 1 + p
                 slots = [8 * R + 4 * half + s for s in range(4)] + [8 * C + s for s in range(8)]
-                for w in range(4):
+                for w in range(8):
                     c0 = 4 + 4 * (w % 2)
-                    for r in (2 * (w // 2), 2 * (w // 2) + 1):
-                        for k in range(4):
-                            out.append((slots[r], slots[c0 + k]))
+                    out += [(slots[w // 2], slots[c0 + k]) for k in range(4)]
         return out
     for nb in (1, 2, 3, 7, 8, 9, 15, 16, 17, 33, 64, 128):
-        tiles = [t for t in groups(nb) if t[0] < nb and t[1] < nb]
+        allt = groups(nb)
+        assert all(i <= j for i, j in allt)
+        tiles = [t for t in allt if t[0] < nb and t[1] < nb]
         want = [(i, j) for i in range(nb) for j in range(i, nb)]
         assert sorted(tiles) == want, nb
-        assert all(i <= j for i, j in groups(nb) if j < nb)
