@@ -34,8 +34,10 @@
  *
  * Calls are asynchronous: they validate their arguments on the host,
  * enqueue kernels on `stream` (a hipStream_t; NULL = the null stream of the
- * handle's device) and return.  They allocate nothing and do not
- * synchronise, so they may be captured into a HIP graph.  Argument errors
+ * handle's device) and return.  They allocate nothing, and all but
+ * xe_accumulate_batch and xe_batch_plan (which upload a work list) enqueue
+ * kernels only and never synchronise, so they may be captured into a HIP
+ * graph.  Argument errors
  * are reported before anything is enqueued; launch errors are reported as
  * XE_ERR_HIP; errors during execution surface at the caller's next
  * synchronisation.  A handle is not thread-safe: use one per host thread.
@@ -68,8 +70,10 @@ typedef int32_t xe_status;
 #define XE_DEVICE_NONE (-1)
 
 /* Create a handle on HIP device `hip_device`.  `workspace_bytes` of device
- * memory is allocated here, once, for batched work lists (0 = a default of
- * a few MB); no later call allocates.  With hip_device == XE_DEVICE_NONE the
+ * memory is allocated here, once, for the sums of time chunks that are
+ * integrated by different workgroups (0 = the default, 1 GiB), beside 32 MB
+ * for batch work lists; no later call allocates.  xe_plan_query and
+ * xe_batch_query assume the default size.  With hip_device == XE_DEVICE_NONE the
  * handle is validation-only: every compute call checks its arguments and
  * then returns XE_ERR_NO_DEVICE without touching memory (for host tests).
  * Errors: XE_ERR_ARG (out == NULL), XE_ERR_HIP, XE_ERR_UNSUPPORTED. */
@@ -120,16 +124,46 @@ typedef struct {
     int64_t *count;
 } xe_instance;
 
-/* Accumulate every instance of the batch in one persistent launch (the
- * paper pre-queues whole chains of operations to hide launch latency,
- * Sec. II-B; several streams share one GPU, Sec. II).  Each instance is
- * validated as for xe_accumulate.  The work list is written into the
- * handle's workspace with one asynchronous host-to-device copy on `stream`;
- * XE_ERR_WORKSPACE when it does not fit.  The list must stay unchanged until
- * the launch has run, so a second batch on the same handle is ordered after
- * the first on the same stream (or the caller synchronises). */
+/* Accumulate every instance of the batch in one persistent launch: the paper
+ * pre-queues whole chains of operations to hide launch latency (Sec. II-B)
+ * and several streams share one GPU (Sec. II).  The instances' work is cut
+ * into items (channel x tile group x time chunk), longest first, and a grid
+ * of one workgroup per compute unit drains them from a device queue.  Each
+ * instance is validated as for xe_accumulate; the work list is copied to
+ * one of four device slots with an asynchronous host-to-device copy from
+ * pinned memory on `stream` (a slot is reused once the launch that last
+ * used it has finished, which the call waits for).  Instances whose frame
+ * is not 4-byte aligned or whose N is not a multiple of 4 run as plain
+ * launches after the batch.  XE_ERR_WORKSPACE when the work list or the
+ * time-chunk sums do not fit.  Like every call on a handle, batches must be
+ * ordered on one stream (they share the handle's workspace). */
 xe_status xe_accumulate_batch(xe_handle h, const xe_instance *inst,
                               int32_t n_inst, void *stream);
+
+/* The same work list, built once and kept on the device (up to four plans
+ * per handle) so that xe_batch_run can be replayed, e.g. from a captured
+ * HIP graph: xe_batch_run only enqueues kernels (no copies, no host
+ * synchronisation, no memset).  chunk_steps = time-chunk length in 32-sample
+ * steps (0: automatic; the tuner in the Python package picks it).  The
+ * plan keeps the instances' pointers: the caller keeps those buffers alive
+ * and refills them between runs.  xe_batch_plan synchronises the device
+ * upload; *plan_id receives the plan. */
+xe_status xe_batch_plan(xe_handle h, const xe_instance *inst, int32_t n_inst,
+                        int32_t chunk_steps, int32_t *plan_id);
+xe_status xe_batch_run(xe_handle h, int32_t plan_id, void *stream);
+xe_status xe_batch_release(xe_handle h, int32_t plan_id);
+
+/* Shape of a batch's work list (host only, no GPU). */
+typedef struct {
+    int64_t items;           /* work items in the persistent launch        */
+    int32_t instances;       /* instances in the persistent launch         */
+    int32_t unaligned;       /* instances run as plain launches            */
+    int32_t chunk_steps;     /* time-chunk length used, in 32-sample steps */
+    int64_t partial_bytes;   /* workspace for time-chunk sums              */
+} xe_batch_info;
+
+xe_status xe_batch_query(const xe_instance *inst, int32_t n_inst, int32_t n_cu,
+                         int32_t chunk_steps, xe_batch_info *info);
 
 /* How the library splits one frame into workgroups (host only, no GPU):
  * validates (N, F, T, B) as the compute calls do. */

@@ -697,6 +697,30 @@ __device__ __forceinline__ int64_t xcd_local_index(int64_t b, int64_t total) {
     return x * per + (x < rem ? x : rem) + idx;
 }
 
+// One work item: tile group gid of channel f over time chunk `split`.
+// Every wave runs the same number of steps and barriers; the tile pattern is
+// fixed per group kind (blocks past N are staged as zeros).
+template <bool kAligned, bool kOverwrite>
+__device__ __forceinline__ void run_item(const CorrArgs &a, int f, int gid, int split,
+                                         uint8_t *lds, uint32_t *mwords, int *s_flag) {
+    const Group g = make_group(a.nb, gid);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (g.diag) {
+        if (wave < 2)  // rows 2w, 2w+1 x columns 4..7
+            run_wave<kAligned, kOverwrite, 8, kRect>(a, g, f, gid, split, 2 * wave, 4, lds,
+                                                     mwords, s_flag);
+        else           // triangle of blocks 4(w-2) .. 4(w-2)+3
+            run_wave<kAligned, kOverwrite, 8, kTri>(a, g, f, gid, split, 4 * (wave - 2), 0, lds,
+                                                    mwords, s_flag);
+    } else {
+        // rows 2(w/2), 2(w/2)+1 x column slots 4 + 4(w%2) .. +3
+        run_wave<kAligned, kOverwrite, 12, kRect>(a, g, f, gid, split, 2 * (wave / 2),
+                                                  4 + 4 * (wave % 2), lds, mwords, s_flag);
+    }
+}
+
+// One frame: workgroup -> (channel, group, chunk), groups of a channel
+// and chunks of a (channel, group) numbered next to each other.
 template <bool kAligned, bool kOverwrite>
 __global__ __launch_bounds__(kThreads, 1) void corr_kernel(CorrArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
@@ -710,23 +734,86 @@ __global__ __launch_bounds__(kThreads, 1) void corr_kernel(CorrArgs a) {
     w /= G;
     const int split = (int)(w % a.splits);
     const int f = (int)(w / a.splits);
+    run_item<kAligned, kOverwrite>(a, f, gid, split, lds, mwords, &s_flag);
+}
 
-    const Group g = make_group(a.nb, gid);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+// ---------------------------------------------------------------------------
+// batched persistent launch
+// ---------------------------------------------------------------------------
 
-    // Every wave runs the same number of steps and barriers; the tile
-    // pattern is fixed per group kind (blocks past N are staged as zeros).
-    if (g.diag) {
-        if (wave < 2)  // rows 2w, 2w+1 x columns 4..7
-            run_wave<kAligned, kOverwrite, 8, kRect>(a, g, f, gid, split, 2 * wave, 4, lds,
-                                                     mwords, &s_flag);
-        else           // triangle of blocks 4(w-2) .. 4(w-2)+3
-            run_wave<kAligned, kOverwrite, 8, kTri>(a, g, f, gid, split, 4 * (wave - 2), 0, lds,
-                                                    mwords, &s_flag);
-    } else {
-        // rows 2(w/2), 2(w/2)+1 x column slots 4 + 4(w%2) .. +3
-        run_wave<kAligned, kOverwrite, 12, kRect>(a, g, f, gid, split, 2 * (wave / 2),
-                                                  4 + 4 * (wave % 2), lds, mwords, &s_flag);
+// One correlator instance of a batch, as the kernel sees it.
+struct BatchInstance {
+    const uint8_t *packed;
+    const uint8_t *mask;
+    int32_t *vis;
+    int64_t *count;
+    int32_t N, F, T, B;
+    int32_t nblk_mask, nb, groups, splits;
+    int32_t steps_per_split, aligned;
+    int64_t counter_base;  // first arrival counter of this instance
+    int64_t partial_base;  // first int32 of its partial tiles
+};
+
+struct BatchItem {
+    int32_t inst, f, gid, split;
+};
+
+// A grid of one workgroup per CU pulls work items from a queue until it is
+// empty (every workgroup reaches the exit).  The last workgroup to finish
+// resets the queue, so the next launch of the same plan starts clean and
+// the launch can be replayed from a graph.  Items are accumulated into their
+// instances' resident sums.  Instances must take the dword-load path
+// (N % 4 == 0, 4-byte aligned frame); the host runs others on their own.
+__global__ __launch_bounds__(kThreads, 1) void batch_kernel(const BatchInstance *inst,
+                                                            const BatchItem *items, int n_items,
+                                                            int *queue, int32_t *counters,
+                                                            int32_t *partials) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
+    __shared__ uint32_t mwords[kMaskWindow];
+    __shared__ int s_flag;
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();  // the previous item has released LDS
+        if (threadIdx.x == 0) s_item = atomicAdd(&queue[0], 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar loads below
+        if (it >= n_items) break;
+        // every field is wave-uniform: readfirstlane keeps them in scalar
+        // registers (buffer resources and offsets must live there)
+        auto u32 = [](int32_t v) { return (int32_t)__builtin_amdgcn_readfirstlane(v); };
+        auto u64 = [](int64_t v) {
+            uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+            uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+            return (int64_t)(((uint64_t)hi << 32) | lo);
+        };
+        auto ptr = [&](const void *p) { return (void *)(uintptr_t)u64((int64_t)(uintptr_t)p); };
+        const BatchItem w = items[it];
+        const int wi = u32(w.inst), wf = u32(w.f), wg = u32(w.gid), ws = u32(w.split);
+        const BatchInstance &bi = inst[wi];
+        CorrArgs a;
+        a.packed = (const uint8_t *)ptr(bi.packed);
+        a.mask = (const uint8_t *)ptr(bi.mask);
+        a.vis = (int32_t *)ptr(bi.vis);
+        a.count = (int64_t *)ptr(bi.count);
+        a.partials = partials + u64(bi.partial_base);
+        a.counters = counters + u64(bi.counter_base);
+        a.N = u32(bi.N);
+        a.F = u32(bi.F);
+        a.T = u32(bi.T);
+        a.B = u32(bi.B);
+        a.nblk_mask = u32(bi.nblk_mask);
+        a.nb = u32(bi.nb);
+        a.groups = u32(bi.groups);
+        a.splits = u32(bi.splits);
+        a.steps_per_split = u32(bi.steps_per_split);
+        run_item<true, false>(a, wf, wg, ws, lds, mwords, &s_flag);
+    }
+    if (threadIdx.x == 0) {
+        int done = atomicAdd(&queue[1], 1);
+        if (done == (int)gridDim.x - 1) {
+            queue[0] = 0;
+            queue[1] = 0;
+        }
     }
 }
 

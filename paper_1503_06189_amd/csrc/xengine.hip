@@ -6,18 +6,41 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/xengine.h"
 #include "plan.hpp"
 #include "xcorr_kernels.hpp"
+
+// Batch plans live in a device area allocated with the handle: kRingSlots
+// slots that xe_accumulate_batch cycles through (each guarded by an event,
+// with a pinned host staging copy) and kPlanSlots slots for plans made with
+// xe_batch_plan and replayed with xe_batch_run.
+constexpr int kRingSlots = 4;
+constexpr int kPlanSlots = 4;
+constexpr size_t kSlotBytes = (size_t)4 << 20;
+constexpr size_t kQueueBytes = 256;  // queue head and done counters, padded
+
+struct PlanSlot {
+    bool used = false;
+    int n_items = 0;
+    int n_inst = 0;
+    std::vector<xe_instance> unaligned;  // instances run as plain launches
+};
 
 struct xe_handle_s {
     int device;          // XE_DEVICE_NONE for a validation-only handle
     int n_cu;
     void *workspace;
     size_t workspace_bytes;
+    void *plan_area;     // (kRingSlots + kPlanSlots) x kSlotBytes, device
+    void *staging;       // kRingSlots x kSlotBytes, pinned host
+    hipEvent_t ring_done[kRingSlots];
+    int ring_next;
+    PlanSlot slots[kRingSlots + kPlanSlots];
     std::string last_error;
 };
 
@@ -80,6 +103,9 @@ xe_status check_frame(xe_handle h, const uint8_t *packed, int32_t N, int32_t F, 
 
 // Workspace layout: [counters: kCounterBytes][partial accumulators ...]
 constexpr size_t kCounterBytes = 1u << 20;
+// default workspace: time-chunk sums of a large batch (327 KB per chunked
+// tile group) with room to spare; small next to 288 GB of HBM
+constexpr size_t kDefaultWorkspace = (size_t)1 << 30;
 constexpr int64_t kMaxKeys = kCounterBytes / sizeof(int32_t);
 
 size_t partial_bytes(int64_t keys, int splits) {
@@ -161,6 +187,157 @@ xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, i
     return XE_OK;
 }
 
+void release_device_memory(xe_handle h) {
+    for (int k = 0; k < kRingSlots; ++k)
+        if (h->ring_done[k]) (void)hipEventDestroy(h->ring_done[k]);
+    if (h->staging) (void)hipHostFree(h->staging);
+    if (h->plan_area) (void)hipFree(h->plan_area);
+    if (h->workspace) (void)hipFree(h->workspace);
+    h->staging = h->plan_area = h->workspace = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// batch planning (host)
+// ---------------------------------------------------------------------------
+
+struct BatchPlan {
+    std::vector<xe::BatchInstance> inst;
+    std::vector<xe::BatchItem> items;
+    std::vector<xe_instance> unaligned;
+    int chunk_steps = 0;
+    int64_t counters = 0;    // arrival counters used
+    int64_t partials = 0;    // int32 partial values used
+};
+
+// Work items of a batch: every (instance, channel, group, time chunk), with
+// time chunks of about `chunk_steps` 32-sample steps (0: enough items for
+// about four per compute unit), longest first so the queue drains evenly.
+xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int n_cu,
+                      int32_t chunk_steps, size_t ws_bytes, BatchPlan *plan) {
+    if (n_inst < 0 || (n_inst > 0 && !inst)) return fail(h, XE_ERR_ARG, "bad batch arguments");
+    if (chunk_steps < 0) return fail(h, XE_ERR_ARG, "chunk_steps must be >= 0");
+    int64_t work = 0;
+    for (int32_t k = 0; k < n_inst; ++k) {
+        const xe_instance &x = inst[k];
+        xe_status s = check_frame(h, x.packed, x.N, x.F, x.T, x.B, x.vis, x.count);
+        if (s != XE_OK) return s;
+        int nb = xe::ceil_div(x.N, xe::kBlk);
+        work += (int64_t)x.F * xe::groups_per_channel(nb) * xe::ceil_div(x.T, xe::kStep);
+    }
+    // instances of one launch update their sums without atomics, so their
+    // output ranges must be disjoint
+    {
+        struct Range {
+            uintptr_t lo, hi;
+        };
+        std::vector<Range> r;
+        for (int32_t k = 0; k < n_inst; ++k) {
+            const xe_instance &x = inst[k];
+            uintptr_t v = (uintptr_t)x.vis, c = (uintptr_t)x.count;
+            r.push_back({v, v + (uintptr_t)x.F * ((uintptr_t)x.N * (x.N + 1) / 2) * 8});
+            r.push_back({c, c + (uintptr_t)x.F * 8});
+        }
+        std::sort(r.begin(), r.end(), [](const Range &a, const Range &b) { return a.lo < b.lo; });
+        for (size_t k = 1; k < r.size(); ++k)
+            if (r[k].lo < r[k - 1].hi)
+                return fail(h, XE_ERR_ARG, "batch instances share output memory");
+    }
+    if (chunk_steps == 0) {
+        int64_t c = work / (4 * (int64_t)n_cu);
+        chunk_steps = (int)std::max<int64_t>(32, std::min<int64_t>(c, xe::kMaxStepsPerChunk));
+    }
+    plan->chunk_steps = chunk_steps;
+    struct Cost {
+        int64_t steps;
+        xe::BatchItem item;
+    };
+    std::vector<Cost> costs;
+    for (int32_t k = 0; k < n_inst; ++k) {
+        const xe_instance &x = inst[k];
+        if (!aligned(x.packed, 4) || x.N % 4 != 0) {
+            plan->unaligned.push_back(x);
+            continue;
+        }
+        const int nb = xe::ceil_div(x.N, xe::kBlk);
+        const int G = xe::groups_per_channel(nb);
+        const int steps = xe::ceil_div(x.T, xe::kStep);
+        int64_t max_sps = ((((int64_t)1 << 31) - 1) / ((int64_t)x.F * x.N * xe::kStep)) - 1;
+        max_sps = std::min<int64_t>(max_sps, xe::kMaxStepsPerChunk);
+        int sps = (int)std::min<int64_t>(std::min<int64_t>(chunk_steps, steps), max_sps);
+        int splits = xe::ceil_div(steps, sps);
+        sps = xe::ceil_div(steps, splits);
+        xe::BatchInstance b;
+        b.packed = x.packed;
+        b.mask = x.loss_mask;
+        b.vis = x.vis;
+        b.count = x.count;
+        b.N = x.N;
+        b.F = x.F;
+        b.T = x.T;
+        b.B = x.B;
+        b.nblk_mask = xe::ceil_div(x.T, x.B);
+        b.nb = nb;
+        b.groups = G;
+        b.splits = splits;
+        b.steps_per_split = sps;
+        b.aligned = 1;
+        b.counter_base = plan->counters;
+        b.partial_base = plan->partials;
+        if (splits > 1) {
+            plan->counters += (int64_t)x.F * G;
+            plan->partials += (int64_t)x.F * G * splits * xe::kGroupPartial;
+        }
+        const int idx = (int)plan->inst.size();
+        plan->inst.push_back(b);
+        for (int f = 0; f < x.F; ++f)
+            for (int gid = 0; gid < G; ++gid)
+                for (int sp = 0; sp < splits; ++sp) {
+                    int64_t len = std::min<int64_t>(sps, steps - (int64_t)sp * sps);
+                    costs.push_back({len, {idx, f, gid, sp}});
+                }
+    }
+    std::stable_sort(costs.begin(), costs.end(),
+                     [](const Cost &a, const Cost &b) { return a.steps > b.steps; });
+    plan->items.reserve(costs.size());
+    for (const Cost &c : costs) plan->items.push_back(c.item);
+    if (plan->counters > kMaxKeys ||
+        kCounterBytes + (size_t)plan->partials * sizeof(int32_t) > ws_bytes)
+        return fail(h, XE_ERR_WORKSPACE, "batch partial sums do not fit the workspace");
+    size_t bytes = kQueueBytes + plan->inst.size() * sizeof(xe::BatchInstance) +
+                   plan->items.size() * sizeof(xe::BatchItem);
+    if (bytes > kSlotBytes) return fail(h, XE_ERR_WORKSPACE, "batch work list too large");
+    return XE_OK;
+}
+
+// Serialise a plan into slot layout: [queue][instances][items].
+void write_plan(const BatchPlan &p, char *dst) {
+    memset(dst, 0, kQueueBytes);
+    char *q = dst + kQueueBytes;
+    memcpy(q, p.inst.data(), p.inst.size() * sizeof(xe::BatchInstance));
+    q += p.inst.size() * sizeof(xe::BatchInstance);
+    memcpy(q, p.items.data(), p.items.size() * sizeof(xe::BatchItem));
+}
+
+size_t plan_bytes(const BatchPlan &p) {
+    return kQueueBytes + p.inst.size() * sizeof(xe::BatchInstance) +
+           p.items.size() * sizeof(xe::BatchItem);
+}
+
+xe_status launch_batch(xe_handle h, int slot, int n_inst, int n_items, hipStream_t stream) {
+    if (n_items == 0) return XE_OK;
+    char *base = (char *)h->plan_area + (size_t)slot * kSlotBytes;
+    const xe::BatchInstance *bi = (const xe::BatchInstance *)(base + kQueueBytes);
+    const xe::BatchItem *items = (const xe::BatchItem *)(base + kQueueBytes +
+                                                           n_inst * sizeof(xe::BatchInstance));
+    int grid = std::min(h->n_cu, n_items);
+    hipLaunchKernelGGL(xe::batch_kernel, dim3(grid), dim3(xe::kThreads), 0, stream, bi, items,
+                       n_items, (int *)base, (int32_t *)h->workspace,
+                       (int32_t *)((char *)h->workspace + kCounterBytes));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "batch launch");
+    return XE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -174,6 +351,10 @@ xe_status xe_create(xe_handle *out, int32_t hip_device, size_t workspace_bytes) 
     h->n_cu = 256;
     h->workspace = nullptr;
     h->workspace_bytes = 0;
+    h->plan_area = nullptr;
+    h->staging = nullptr;
+    h->ring_next = 0;
+    for (int k = 0; k < kRingSlots; ++k) h->ring_done[k] = nullptr;
     if (hip_device == XE_DEVICE_NONE) {
         *out = h;
         return XE_OK;
@@ -195,7 +376,7 @@ xe_status xe_create(xe_handle *out, int32_t hip_device, size_t workspace_bytes) 
         return XE_ERR_UNSUPPORTED;
     }
     h->n_cu = prop.multiProcessorCount;
-    if (workspace_bytes == 0) workspace_bytes = (size_t)256 << 20;
+    if (workspace_bytes == 0) workspace_bytes = kDefaultWorkspace;
     if (workspace_bytes < kCounterBytes) workspace_bytes = kCounterBytes;
     {
         DeviceGuard g(hip_device);
@@ -208,11 +389,18 @@ xe_status xe_create(xe_handle *out, int32_t hip_device, size_t workspace_bytes) 
             delete h;
             return XE_ERR_HIP;
         }
-        // arrival counters start at zero; every launch leaves them at zero
+        // arrival counters and batch queues start at zero; every launch
+        // leaves them at zero
         e = hipMemset(h->workspace, 0, kCounterBytes);
+        if (e == hipSuccess) e = hipMalloc(&h->plan_area, (kRingSlots + kPlanSlots) * kSlotBytes);
+        if (e == hipSuccess)
+            e = hipMemset(h->plan_area, 0, (kRingSlots + kPlanSlots) * kSlotBytes);
+        if (e == hipSuccess) e = hipHostMalloc(&h->staging, kRingSlots * kSlotBytes, 0);
+        for (int k = 0; k < kRingSlots && e == hipSuccess; ++k)
+            e = hipEventCreateWithFlags(&h->ring_done[k], hipEventDisableTiming);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) {
-            (void)hipFree(h->workspace);
+            release_device_memory(h);
             delete h;
             return XE_ERR_HIP;
         }
@@ -224,9 +412,9 @@ xe_status xe_create(xe_handle *out, int32_t hip_device, size_t workspace_bytes) 
 
 xe_status xe_destroy(xe_handle h) {
     if (!h) return XE_OK;
-    if (h->workspace) {
+    if (h->device != XE_DEVICE_NONE) {
         DeviceGuard g(h->device);
-        (void)hipFree(h->workspace);
+        release_device_memory(h);
     }
     delete h;
     return XE_OK;
@@ -254,7 +442,7 @@ xe_status xe_plan_query(int32_t N, int32_t F, int32_t T, int32_t B, int32_t n_cu
     xe_status s = check_shape(nullptr, N, F, T, B);
     if (s != XE_OK) return s;
     if (n_cu < 1) return XE_ERR_ARG;
-    if (!fill_plan(N, F, T, n_cu, (size_t)256 << 20, info)) return XE_ERR_WORKSPACE;
+    if (!fill_plan(N, F, T, n_cu, kDefaultWorkspace, info)) return XE_ERR_WORKSPACE;
     return XE_OK;
 }
 
@@ -313,19 +501,110 @@ xe_status xe_normalize(xe_handle h, const int32_t *vis, const int64_t *count, in
 
 xe_status xe_accumulate_batch(xe_handle h, const xe_instance *inst, int32_t n_inst,
                               void *stream) {
-    if (!h || !inst || n_inst < 0) return fail(h, XE_ERR_ARG, "bad batch arguments");
-    for (int32_t k = 0; k < n_inst; ++k) {
-        const xe_instance &x = inst[k];
-        xe_status s = check_frame(h, x.packed, x.N, x.F, x.T, x.B, x.vis, x.count);
-        if (s != XE_OK) return s;
-    }
+    if (!h) return XE_ERR_ARG;
+    BatchPlan plan;
+    xe_status s = build_batch(h, inst, n_inst, h->n_cu, 0,
+                              h->device == XE_DEVICE_NONE ? kDefaultWorkspace
+                                                          : h->workspace_bytes, &plan);
+    if (s != XE_OK) return s;
     if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
-    for (int32_t k = 0; k < n_inst; ++k) {
-        const xe_instance &x = inst[k];
-        xe_status s = xe_accumulate(h, x.packed, x.loss_mask, x.N, x.F, x.T, x.B, x.vis,
-                                    x.count, stream);
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    if (!plan.items.empty()) {
+        // the ring slot (and its pinned staging copy) is free once the
+        // launch that last used it has finished
+        const int slot = h->ring_next;
+        h->ring_next = (h->ring_next + 1) % kRingSlots;
+        hipError_t e = hipEventSynchronize(h->ring_done[slot]);
+        if (e != hipSuccess) return hip_fail(h, e, "batch ring wait");
+        char *stage = (char *)h->staging + (size_t)slot * kSlotBytes;
+        write_plan(plan, stage);
+        e = hipMemcpyAsync((char *)h->plan_area + (size_t)slot * kSlotBytes, stage,
+                           plan_bytes(plan), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(h, e, "batch upload");
+        s = launch_batch(h, slot, (int)plan.inst.size(), (int)plan.items.size(), st);
+        if (s != XE_OK) return s;
+        e = hipEventRecord(h->ring_done[slot], st);
+        if (e != hipSuccess) return hip_fail(h, e, "batch ring record");
+    }
+    for (const xe_instance &x : plan.unaligned) {
+        s = launch_corr(h, x.packed, x.loss_mask, x.N, x.F, x.T, x.B, x.vis, x.count, false, st);
         if (s != XE_OK) return s;
     }
+    return XE_OK;
+}
+
+xe_status xe_batch_plan(xe_handle h, const xe_instance *inst, int32_t n_inst,
+                        int32_t chunk_steps, int32_t *plan_id) {
+    if (!h || !plan_id) return XE_ERR_ARG;
+    BatchPlan plan;
+    xe_status s = build_batch(h, inst, n_inst, h->n_cu, chunk_steps,
+                              h->device == XE_DEVICE_NONE ? kDefaultWorkspace
+                                                          : h->workspace_bytes, &plan);
+    if (s != XE_OK) return s;
+    if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
+    int slot = -1;
+    for (int k = kRingSlots; k < kRingSlots + kPlanSlots; ++k)
+        if (!h->slots[k].used) {
+            slot = k;
+            break;
+        }
+    if (slot < 0) return fail(h, XE_ERR_WORKSPACE, "all plan slots in use");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
+    std::vector<char> host(plan_bytes(plan));
+    write_plan(plan, host.data());
+    hipError_t e = hipMemcpy((char *)h->plan_area + (size_t)slot * kSlotBytes, host.data(),
+                             host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(h, e, "plan upload");
+    PlanSlot &ps = h->slots[slot];
+    ps.used = true;
+    ps.n_items = (int)plan.items.size();
+    ps.unaligned = plan.unaligned;
+    ps.n_inst = (int)plan.inst.size();
+    *plan_id = slot;
+    return XE_OK;
+}
+
+xe_status xe_batch_run(xe_handle h, int32_t plan_id, void *stream) {
+    if (!h || plan_id < kRingSlots || plan_id >= kRingSlots + kPlanSlots ||
+        !h->slots[plan_id].used)
+        return fail(h, XE_ERR_ARG, "unknown plan");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
+    const PlanSlot &ps = h->slots[plan_id];
+    hipStream_t st = (hipStream_t)stream;
+    xe_status s = launch_batch(h, plan_id, ps.n_inst, ps.n_items, st);
+    if (s != XE_OK) return s;
+    for (const xe_instance &x : ps.unaligned) {
+        s = launch_corr(h, x.packed, x.loss_mask, x.N, x.F, x.T, x.B, x.vis, x.count, false, st);
+        if (s != XE_OK) return s;
+    }
+    return XE_OK;
+}
+
+xe_status xe_batch_release(xe_handle h, int32_t plan_id) {
+    if (!h || plan_id < kRingSlots || plan_id >= kRingSlots + kPlanSlots ||
+        !h->slots[plan_id].used)
+        return fail(h, XE_ERR_ARG, "unknown plan");
+    h->slots[plan_id] = PlanSlot();
+    return XE_OK;
+}
+
+xe_status xe_batch_query(const xe_instance *inst, int32_t n_inst, int32_t n_cu,
+                         int32_t chunk_steps, xe_batch_info *info) {
+    if (!info || n_cu < 1) return XE_ERR_ARG;
+    BatchPlan plan;
+    xe_handle_s probe{};  // validation only: never touches a device
+    probe.device = XE_DEVICE_NONE;
+    xe_status s = build_batch(&probe, inst, n_inst, n_cu, chunk_steps, kDefaultWorkspace, &plan);
+    if (s != XE_OK) return s;
+    info->items = (int64_t)plan.items.size();
+    info->instances = (int32_t)plan.inst.size();
+    info->unaligned = (int32_t)plan.unaligned.size();
+    info->chunk_steps = plan.chunk_steps;
+    info->partial_bytes = plan.partials * (int64_t)sizeof(int32_t);
     return XE_OK;
 }
 

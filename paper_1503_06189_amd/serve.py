@@ -1,0 +1,470 @@
+"""Streaming correlator: several input streams share one GPU (Sec. II).
+
+Frames arrive from the network side in pinned host memory (the ring
+buffers of Sec. II-A).  The server
+
+* admits a frame to the device only while the HBM it needs fits a fixed
+  budget (frame buffers in flight plus every open stream's resident
+  accumulators), so a burst waits in host memory instead of failing;
+* copies admitted frames host-to-device on a copy stream;
+* launches, whenever the GPU has room, ONE persistent batched launch over
+  the oldest ready frame of every stream (continuous batching: frames that
+  arrive while a batch runs join the next one);
+* keeps each stream's integration resident on the device, adding frame
+  after frame (Sec. II-B), and at the end of an integration normalises it
+  for lost samples (Sec. II-C) and copies it out, while the stream's next
+  integration proceeds in a second accumulator.
+
+Every compute step runs in the library's kernels (xengine); this module
+only schedules them and owns the memory accounting.  Frame latency is
+measured from arrival in pinned memory to the completion of the
+accumulation that consumed the frame, on the GPU's clock.
+"""
+
+from __future__ import annotations
+
+import collections
+import dataclasses
+import queue
+import threading
+import time
+from typing import Callable, Deque, Dict, List, Optional
+
+import numpy as np
+
+from . import xengine
+
+
+@dataclasses.dataclass
+class StreamConfig:
+    stream_id: int
+    N: int
+    F: int
+    T: int                       # samples per frame
+    B: int                       # samples per loss-mask block
+    frames_per_integration: int
+
+
+@dataclasses.dataclass
+class Frame:
+    stream_id: int
+    seq: int
+    packed: "object"             # pinned uint8 [T][F][N] host tensor
+    mask: "object"               # pinned uint8 [F][nblk] host tensor or None
+    t_arrival: float             # time.perf_counter() at arrival
+    # set by the server
+    dev_packed: "object" = None
+    dev_mask: "object" = None
+    ev_copied: "object" = None
+    nbytes: int = 0
+    t_done: float = 0.0
+
+
+@dataclasses.dataclass
+class IntegrationResult:
+    stream_id: int
+    index: int                   # integration number of the stream
+    frames: int
+    vis: np.ndarray              # int32 [F][P][2]
+    count: np.ndarray            # int64 [F]
+    out: np.ndarray              # float32 [F][P][2]
+    t_ready: float
+
+
+class _Stream:
+    def __init__(self, cfg: StreamConfig, device, pinned_results: bool = True):
+        import torch
+        self.cfg = cfg
+        N, F = cfg.N, cfg.F
+        P = N * (N + 1) // 2
+        self.acc = [xengine.new_accumulators(N, F, device) for _ in range(2)]
+        self.out = [torch.empty((F, P, 2), dtype=torch.float32, device=device)
+                    for _ in range(2)]
+        self.host = [(torch.empty((F, P, 2), dtype=torch.int32, pin_memory=pinned_results),
+                      torch.empty((F,), dtype=torch.int64, pin_memory=pinned_results),
+                      torch.empty((F, P, 2), dtype=torch.float32, pin_memory=pinned_results))
+                     for _ in range(2)]
+        self.ev_d2h = [None, None]   # copy-out of buffer k finished
+        self.host_busy = [False, False]  # host copy k not yet taken
+        self.cur = 0
+        self.frames_in = 0           # frames launched into the current integration
+        self.index = 0
+        self.pending: Deque[Frame] = collections.deque()   # admitted, not launched
+        self.waiting: Deque[Frame] = collections.deque()   # arrived, not admitted
+        self.resident_bytes = 2 * (2 * F * P * 8 + F * 8)
+
+    @staticmethod
+    def resident_bytes_for(cfg: StreamConfig) -> int:
+        P = cfg.N * (cfg.N + 1) // 2
+        return 2 * (2 * cfg.F * P * 8 + cfg.F * 8)
+
+
+def frame_bytes(cfg: StreamConfig) -> int:
+    nblk = (cfg.T + cfg.B - 1) // cfg.B
+    return cfg.T * cfg.F * cfg.N + cfg.F * nblk
+
+
+class StreamServer:
+    """Admission, batching and integration of frames from many streams."""
+
+    def __init__(self, hbm_budget: int, device: int = 0, max_inflight: int = 2,
+                 handle: Optional[xengine.Handle] = None,
+                 on_result: Optional[Callable[[IntegrationResult], None]] = None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.budget = int(hbm_budget)
+        self.used = 0
+        self.max_inflight = max_inflight
+        self.h = handle or xengine.default_handle(device)
+        self.copy_stream = torch.cuda.Stream(self.device)
+        self.compute_stream = torch.cuda.Stream(self.device)
+        self.d2h_stream = torch.cuda.Stream(self.device)
+        self.streams: Dict[int, _Stream] = {}
+        self.arrivals: "queue.Queue[Frame]" = queue.Queue()
+        self.inflight: Deque[tuple] = collections.deque()   # (event, frames)
+        self.outgoing: Deque[tuple] = collections.deque()   # (event, stream, k, index, frames)
+        self.results: Dict[int, List[IntegrationResult]] = collections.defaultdict(list)
+        self.on_result = on_result
+        self.latencies: List[float] = []
+        self.bytes_done = 0
+        self.samples_done = 0
+        self.frames_done = 0
+        self.batches = 0
+        self.batch_sizes: List[int] = []
+        self.max_used = 0
+        self.admission_waits = 0
+        # host clock <-> GPU clock: an event recorded and waited for now
+        self._ev_ref = torch.cuda.Event(enable_timing=True)
+        self._ev_ref.record(self.compute_stream)
+        self._ev_ref.synchronize()
+        self._t_ref = time.perf_counter()
+
+    # -- streams ----------------------------------------------------------
+
+    def open(self, cfg: StreamConfig) -> None:
+        if cfg.stream_id in self.streams:
+            raise ValueError(f"stream {cfg.stream_id} already open")
+        need = _Stream.resident_bytes_for(cfg)
+        if need + frame_bytes(cfg) > self.budget - self.used:
+            raise MemoryError(
+                f"stream {cfg.stream_id}: accumulators ({need} B) plus one frame do not fit "
+                f"the HBM budget ({self.budget - self.used} B free)")
+        self.used += need
+        self.max_used = max(self.max_used, self.used)
+        with self.torch.cuda.stream(self.compute_stream):
+            self.streams[cfg.stream_id] = _Stream(cfg, self.device)
+
+    def close(self, stream_id: int) -> None:
+        """Forget a stream whose frames have all been integrated."""
+        s = self.streams[stream_id]
+        if s.pending or s.waiting or s.frames_in:
+            raise RuntimeError(f"stream {stream_id} still has frames")
+        self.sync()
+        self.used -= s.resident_bytes
+        del self.streams[stream_id]
+
+    # -- input --------------------------------------------------------------
+
+    def submit(self, frame: Frame) -> None:
+        """Hand over a frame in pinned host memory (thread-safe)."""
+        if frame.t_arrival <= 0:
+            frame.t_arrival = time.perf_counter()
+        self.arrivals.put(frame)
+
+    # -- scheduling ---------------------------------------------------------
+
+    def _gpu_time(self, ev) -> float:
+        return self._t_ref + self._ev_ref.elapsed_time(ev) / 1e3
+
+    def _admit(self) -> None:
+        torch = self.torch
+        while True:
+            try:
+                fr = self.arrivals.get_nowait()
+            except queue.Empty:
+                break
+            s = self.streams.get(fr.stream_id)
+            if s is None:
+                raise KeyError(f"frame for unopened stream {fr.stream_id}")
+            s.waiting.append(fr)
+        # oldest first across streams
+        order = sorted((s.waiting[0].t_arrival, sid) for sid, s in self.streams.items()
+                       if s.waiting)
+        for _, sid in order:
+            s = self.streams[sid]
+            while s.waiting:
+                fr = s.waiting[0]
+                cfg = s.cfg
+                nb = frame_bytes(cfg)
+                if self.used + nb > self.budget:
+                    self.admission_waits += 1
+                    return          # keep arrival order: nothing younger overtakes
+                s.waiting.popleft()
+                self.used += nb
+                self.max_used = max(self.max_used, self.used)
+                fr.nbytes = nb
+                if fr.packed.is_cuda:       # already in HBM: nothing to copy
+                    fr.dev_packed, fr.dev_mask = fr.packed, fr.mask
+                    fr.ev_copied = None
+                    s.pending.append(fr)
+                    continue
+                with torch.cuda.stream(self.copy_stream):
+                    fr.dev_packed = fr.packed.to(self.device, non_blocking=True)
+                    fr.dev_mask = (fr.mask.to(self.device, non_blocking=True)
+                                   if fr.mask is not None else None)
+                    fr.ev_copied = torch.cuda.Event()
+                    fr.ev_copied.record(self.copy_stream)
+                s.pending.append(fr)
+
+    def _launch(self) -> bool:
+        torch = self.torch
+        if len(self.inflight) >= self.max_inflight:
+            return False
+        batch = []
+        for sid, s in self.streams.items():
+            if s.pending:
+                batch.append((s, s.pending.popleft()))
+        if not batch:
+            return False
+        cs = self.compute_stream
+        items = []
+        for s, fr in batch:
+            if fr.ev_copied is not None:
+                cs.wait_event(fr.ev_copied)
+            # the device tensors were made on the copy stream: keep their
+            # memory from being reused before the compute stream is done
+            fr.dev_packed.record_stream(cs)
+            if fr.dev_mask is not None:
+                fr.dev_mask.record_stream(cs)
+            vis, cnt = s.acc[s.cur]
+            items.append((fr.dev_packed, fr.dev_mask, s.cfg.B, vis, cnt))
+        xengine.accumulate_batch(items, handle=self.h, stream=cs)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(cs)
+        self.inflight.append((ev, [fr for _, fr in batch]))
+        self.batches += 1
+        self.batch_sizes.append(len(batch))
+        # integrations that this batch completes: normalise, copy out, and
+        # switch the stream to its other accumulator
+        for s, fr in batch:
+            s.frames_in += 1
+            if s.frames_in < s.cfg.frames_per_integration:
+                continue
+            k = s.cur
+            vis, cnt = s.acc[k]
+            xengine.normalize(vis, cnt, s.out[k], handle=self.h, stream=cs)
+            ev_norm = torch.cuda.Event()
+            ev_norm.record(cs)
+            # the host copy of buffer k (two integrations ago) must have
+            # been taken: its copy-out is long done, collect it
+            if s.host_busy[k]:
+                s.ev_d2h[k].synchronize()
+                self._complete()
+            assert not s.host_busy[k]
+            s.host_busy[k] = True
+            hv, hc, ho = s.host[k]
+            self.d2h_stream.wait_event(ev_norm)
+            with torch.cuda.stream(self.d2h_stream):
+                hv.copy_(vis, non_blocking=True)
+                hc.copy_(cnt, non_blocking=True)
+                ho.copy_(s.out[k], non_blocking=True)
+                ev_d2h = torch.cuda.Event(enable_timing=True)
+                ev_d2h.record(self.d2h_stream)
+            s.ev_d2h[k] = ev_d2h
+            self.outgoing.append((ev_d2h, s, k, s.index, s.frames_in))
+            s.index += 1
+            s.frames_in = 0
+            s.cur ^= 1
+            nk = s.cur
+            # the other accumulator starts from zero once its last copy-out
+            # has read it
+            if s.ev_d2h[nk] is not None:
+                cs.wait_event(s.ev_d2h[nk])
+            with torch.cuda.stream(cs):
+                s.acc[nk][0].zero_()
+                s.acc[nk][1].zero_()
+        return True
+
+    def _complete(self) -> int:
+        n = 0
+        while self.inflight and self.inflight[0][0].query():
+            ev, frames = self.inflight.popleft()
+            t_done = self._gpu_time(ev)
+            for fr in frames:
+                fr.t_done = t_done
+                self.latencies.append(t_done - fr.t_arrival)
+                self.used -= fr.nbytes
+                self.bytes_done += fr.nbytes
+                cfg = self.streams[fr.stream_id].cfg
+                self.samples_done += cfg.N * cfg.F * cfg.T
+                self.frames_done += 1
+                fr.dev_packed = fr.dev_mask = None
+            n += 1
+        while self.outgoing and self.outgoing[0][0].query():
+            ev, s, k, index, frames = self.outgoing.popleft()
+            hv, hc, ho = s.host[k]
+            res = IntegrationResult(s.cfg.stream_id, index, frames, hv.numpy().copy(),
+                                    hc.numpy().copy(), ho.numpy().copy(), self._gpu_time(ev))
+            s.host_busy[k] = False
+            self.results[s.cfg.stream_id].append(res)
+            if self.on_result is not None:
+                self.on_result(res)
+        return n
+
+    def step(self) -> bool:
+        """One scheduling pass; True if anything happened."""
+        done = self._complete()
+        self._admit()
+        launched = False
+        while self._launch():
+            launched = True
+        return bool(done) or launched
+
+    def busy(self) -> bool:
+        return (not self.arrivals.empty() or bool(self.inflight) or bool(self.outgoing) or
+                any(s.pending or s.waiting for s in self.streams.values()))
+
+    def sync(self) -> None:
+        """Run until every submitted frame and finished integration is out."""
+        while self.busy():
+            if not self.step():
+                time.sleep(20e-6)
+
+    def serve(self, stop: threading.Event, idle_sleep: float = 20e-6) -> None:
+        """Scheduling loop until `stop` is set and nothing is left."""
+        while not (stop.is_set() and not self.busy()):
+            if not self.step():
+                time.sleep(idle_sleep)
+
+    # -- reporting ----------------------------------------------------------
+
+    def stats(self, wall_s: float) -> dict:
+        lat = np.array(self.latencies) * 1e3
+        return {
+            "frames": self.frames_done,
+            "batches": self.batches,
+            "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
+            "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+            "max_ms": float(lat.max()) if lat.size else None,
+            "gbps": 8.0 * self.samples_done / wall_s / 1e9 if wall_s > 0 else 0.0,
+            "hbm_budget": self.budget,
+            "hbm_peak_used": self.max_used,
+            "admission_waits": self.admission_waits,
+        }
+
+
+# ---------------------------------------------------------------------------
+# offered load
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class LoadResult:
+    server: StreamServer
+    stats: dict
+    frames: Dict[int, list]          # per stream: the distinct frames (synth.Frame)
+    sequence: Dict[int, List[int]]   # per stream: pool index of each frame, in order
+
+
+def _frame_pool(specs, distinct: int, B: int):
+    from . import synth
+    return {s.stream_id: [synth.stream_frame(s, k, B) for k in range(distinct)]
+            for s in specs}
+
+
+def run_load(specs, frames_per_stream: Optional[int] = None, integrations: int = 1,
+             speed: float = 1.0, hbm_budget: int = 2 << 30, distinct: int = 2,
+             B: int = 256, device: int = 0, max_inflight: int = 2,
+             device_resident: bool = False, seed: int = 0, pool=None,
+             handle: Optional[xengine.Handle] = None) -> LoadResult:
+    """Offer each stream's frames with Poisson arrivals at ``speed`` times
+    its rate (``speed`` = inf: all at once) and serve them.
+
+    Each stream sends ``frames_per_stream`` frames (default: ``integrations``
+    whole integrations), cycling through ``distinct`` generated frames.
+    ``device_resident``: the frames are already in HBM (no host link), to
+    measure the serving loop's own sustained rate."""
+    import torch
+    pool = pool or _frame_pool(specs, distinct, B)
+    dev = torch.device("cuda", device)
+    tens = {}
+    for s in specs:
+        lst = []
+        for fr in pool[s.stream_id]:
+            p = torch.from_numpy(fr.packed)
+            m = torch.from_numpy(fr.mask)
+            if device_resident:
+                lst.append((p.to(dev), m.to(dev)))
+            else:
+                lst.append((p.pin_memory(), m.pin_memory()))
+        tens[s.stream_id] = lst
+    torch.cuda.synchronize(dev)
+    rng = np.random.default_rng(seed)
+    arrivals = []
+    sequence = {}
+    for s in specs:
+        n = frames_per_stream or integrations * s.frames_per_integration
+        rate = s.frame_rate * speed
+        gaps = (rng.exponential(1.0 / rate, n) if np.isfinite(rate) else np.zeros(n))
+        t = np.cumsum(gaps)
+        k_pool = len(tens[s.stream_id])
+        sequence[s.stream_id] = [k % k_pool for k in range(n)]
+        arrivals += [(float(t[k]), s.stream_id, k) for k in range(n)]
+    arrivals.sort()
+    server = StreamServer(hbm_budget, device, max_inflight, handle)
+    for s in specs:
+        server.open(StreamConfig(s.stream_id, s.N, s.F, s.T, B, s.frames_per_integration))
+    stop = threading.Event()
+
+    def produce():
+        t0 = time.perf_counter()
+        for t_off, sid, k in arrivals:
+            delay = t0 + t_off - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            p, m = tens[sid][sequence[sid][k]]
+            server.submit(Frame(sid, k, p, m, time.perf_counter()))
+        stop.set()
+
+    prod = threading.Thread(target=produce, daemon=True)
+    t_start = time.perf_counter()
+    prod.start()
+    server.serve(stop)
+    prod.join()
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t_start
+    st = server.stats(wall)
+    st["wall_s"] = wall
+    st["offered_gbps"] = (sum(s.rate_bps for s in specs) * speed / 1e9
+                          if np.isfinite(speed) else None)
+    st["device_resident"] = device_resident
+    return LoadResult(server, st, pool, sequence)
+
+
+def run_plain(specs, pool, frames_per_stream: int, B: int = 256, device: int = 0,
+              handle: Optional[xengine.Handle] = None) -> dict:
+    """The same frames, device-resident, one plain xe_accumulate launch per
+    frame in arrival order: the baseline the batched server must beat."""
+    import torch
+    dev = torch.device("cuda", device)
+    h = handle or xengine.default_handle(device)
+    acc = {s.stream_id: xengine.new_accumulators(s.N, s.F, dev) for s in specs}
+    tens = {s.stream_id: [(torch.from_numpy(f.packed).to(dev), torch.from_numpy(f.mask).to(dev))
+                          for f in pool[s.stream_id]] for s in specs}
+    order = [(k, s.stream_id) for k in range(frames_per_stream) for s in specs]
+    samples = sum(s.N * s.F * s.T for s in specs) * frames_per_stream
+
+    def once():
+        for k, sid in order:
+            p, m = tens[sid][k % len(tens[sid])]
+            vis, cnt = acc[sid]
+            xengine.accumulate(p, m, B, vis, cnt, handle=h)
+
+    once()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    once()
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    return {"frames": len(order), "wall_s": wall, "gbps": 8.0 * samples / wall / 1e9}

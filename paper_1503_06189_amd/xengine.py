@@ -32,7 +32,8 @@ XE_DEVICE_NONE = -1
 #: every function the header declares
 EXPORTS = ("xe_create", "xe_destroy", "xe_status_string", "xe_last_error",
            "xe_correlate_frame", "xe_accumulate", "xe_normalize",
-           "xe_accumulate_batch", "xe_plan_query")
+           "xe_accumulate_batch", "xe_batch_plan", "xe_batch_run", "xe_batch_release",
+           "xe_batch_query", "xe_plan_query")
 
 
 class XEngineUnavailable(RuntimeError):
@@ -55,6 +56,12 @@ class Instance(ctypes.Structure):
     _fields_ = [("packed", ctypes.c_void_p), ("loss_mask", ctypes.c_void_p),
                 ("N", ctypes.c_int32), ("F", ctypes.c_int32), ("T", ctypes.c_int32),
                 ("B", ctypes.c_int32), ("vis", ctypes.c_void_p), ("count", ctypes.c_void_p)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_int64), ("instances", ctypes.c_int32),
+                ("unaligned", ctypes.c_int32), ("chunk_steps", ctypes.c_int32),
+                ("partial_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -91,6 +98,16 @@ def lib() -> ctypes.CDLL:
             L.xe_normalize.argtypes = [vp, vp, vp, i32, i32, vp, vp]
             L.xe_accumulate_batch.restype = i32
             L.xe_accumulate_batch.argtypes = [vp, ctypes.POINTER(Instance), i32, vp]
+            L.xe_batch_plan.restype = i32
+            L.xe_batch_plan.argtypes = [vp, ctypes.POINTER(Instance), i32, i32,
+                                        ctypes.POINTER(i32)]
+            L.xe_batch_run.restype = i32
+            L.xe_batch_run.argtypes = [vp, i32, vp]
+            L.xe_batch_release.restype = i32
+            L.xe_batch_release.argtypes = [vp, i32]
+            L.xe_batch_query.restype = i32
+            L.xe_batch_query.argtypes = [ctypes.POINTER(Instance), i32, i32, i32,
+                                         ctypes.POINTER(BatchInfo)]
             L.xe_plan_query.restype = i32
             L.xe_plan_query.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(PlanInfo)]
             _lib = L
@@ -248,15 +265,75 @@ def normalize(vis, count, out=None, handle: Optional[Handle] = None, stream=None
     return out
 
 
-def accumulate_batch(items: Sequence[Tuple], handle: Optional[Handle] = None, stream=None):
-    """items: (packed, mask, B, vis, count) per instance; one library call."""
-    arr = (Instance * len(items))()
+def _instances(items: Sequence[Tuple]):
+    """ctypes array of xe_instance from (packed, mask, B, vis, count) tuples."""
+    arr = (Instance * max(1, len(items)))()
     dev = None
     for k, (packed, mask, B, vis, count) in enumerate(items):
         T, F, N = _check_frame(packed, mask, B)
         _check_acc(vis, count, N, F)
+        if dev is not None and packed.device.index != dev:
+            raise ValueError("all instances of a batch must be on one device")
         dev = packed.device.index
         arr[k] = Instance(packed.data_ptr(), mask.data_ptr() if mask is not None else None,
                           N, F, T, B, vis.data_ptr(), count.data_ptr())
+    return arr, dev
+
+
+def accumulate_batch(items: Sequence[Tuple], handle: Optional[Handle] = None, stream=None):
+    """items: (packed, mask, B, vis, count) per instance; one persistent launch."""
+    arr, dev = _instances(items)
     h = handle or default_handle(dev)
     h.check(lib().xe_accumulate_batch(h.ptr, arr, len(items), _stream_ptr(stream)))
+
+
+class BatchPlan:
+    """A work list kept on the device; :meth:`run` only enqueues kernels, so
+    it can be captured into a CUDA/HIP graph and replayed.  The instances'
+    tensors are referenced here so they outlive the plan."""
+
+    def __init__(self, items: Sequence[Tuple], chunk_steps: int = 0,
+                 handle: Optional[Handle] = None):
+        arr, dev = _instances(items)
+        self.handle = handle or default_handle(dev)
+        self.items = list(items)
+        pid = ctypes.c_int32(-1)
+        self.handle.check(lib().xe_batch_plan(self.handle.ptr, arr, len(items), chunk_steps,
+                                              ctypes.byref(pid)))
+        self.plan_id = pid.value
+
+    def run(self, stream=None) -> None:
+        self.handle.check(lib().xe_batch_run(self.handle.ptr, self.plan_id,
+                                             _stream_ptr(stream)))
+
+    def release(self) -> None:
+        if self.plan_id >= 0:
+            lib().xe_batch_release(self.handle.ptr, self.plan_id)
+            self.plan_id = -1
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def batch_query(shapes: Sequence[Tuple[int, int, int, int]], n_cu: int = 256,
+                chunk_steps: int = 0, aligned: Sequence[bool] = ()) -> BatchInfo:
+    """Work-list shape for instances (N, F, T, B), host only.  Fake,
+    disjoint, suitably aligned pointers stand in for device buffers
+    (``aligned[k]`` False offsets instance k's frame by one byte)."""
+    arr = (Instance * max(1, len(shapes)))()
+    base = 1 << 40
+    for k, (N, F, T, B) in enumerate(shapes):
+        P = N * (N + 1) // 2
+        off = 0 if (k >= len(aligned) or aligned[k]) else 1
+        vis = base
+        cnt = vis + ((F * P * 8 + 255) & ~255)
+        arr[k] = Instance(base + off + (1 << 36), None, N, F, T, B, vis, cnt)
+        base = cnt + ((F * 8 + 255) & ~255)
+    info = BatchInfo()
+    s = lib().xe_batch_query(arr, len(shapes), n_cu, chunk_steps, ctypes.byref(info))
+    if s != XE_OK:
+        raise XEngineError(s, status_string(s))
+    return info

@@ -76,11 +76,62 @@ def test_normalize_checks(L, h):
 def test_batch_checks(L, h):
     arr = (xe.Instance * 2)()
     arr[0] = xe.Instance(0x1000, None, 16, 1, 64, 16, 0x2000, 0x3000)
-    arr[1] = xe.Instance(0x1000, None, 16, 1, 64, 16, 0x2000, 0x3000)
+    arr[1] = xe.Instance(0x1000, None, 16, 1, 64, 16, 0x4000, 0x5000)
     assert L.xe_accumulate_batch(h, arr, 2, None) == xe.XE_ERR_NO_DEVICE
+    assert L.xe_accumulate_batch(h, arr, 0, None) == xe.XE_ERR_NO_DEVICE
+    pid = ctypes.c_int32(-1)
+    assert L.xe_batch_plan(h, arr, 2, 0, ctypes.byref(pid)) == xe.XE_ERR_NO_DEVICE
+    assert L.xe_batch_plan(h, arr, 2, -1, ctypes.byref(pid)) == xe.XE_ERR_ARG
+    assert L.xe_batch_run(h, 0, None) == xe.XE_ERR_ARG       # no such plan
+    assert L.xe_batch_run(h, 7, None) == xe.XE_ERR_ARG
+    assert L.xe_batch_release(h, 5) == xe.XE_ERR_ARG
+    # the second instance's sums overlap the first's (16 inputs: 1088 bytes)
+    arr[1].vis = 0x2000 + 1024
+    assert L.xe_accumulate_batch(h, arr, 2, None) == xe.XE_ERR_ARG
+    assert b"share" in L.xe_last_error(h)
+    arr[1].vis = 0x4000
+    arr[1].count = 0x2000 + 8 * 136 - 8
+    assert L.xe_accumulate_batch(h, arr, 2, None) == xe.XE_ERR_ARG
+    arr[1].count = 0x5000
     arr[1].N = 0
     assert L.xe_accumulate_batch(h, arr, 2, None) == xe.XE_ERR_ARG
     assert L.xe_accumulate_batch(h, arr, -1, None) == xe.XE_ERR_ARG
+    assert L.xe_accumulate_batch(h, None, 2, None) == xe.XE_ERR_ARG
+
+
+def test_batch_query_work_list():
+    """Work items = sum over instances of F * groups * time chunks; the
+    automatic chunk length gives about four items per compute unit."""
+    import random
+    rng = random.Random(7)
+    shapes = [(rng.choice([64, 128, 256, 512, 1024]), 1, 256 * rng.randint(4, 256), 256)
+              for _ in range(128)]
+    info = xe.batch_query(shapes, n_cu=256)
+    assert info.instances == 128 and info.unaligned == 0
+    items = 0
+    work = 0
+    for N, F, T, B in shapes:
+        nb = -(-N // 32)
+        G = (-(-nb // 8)) ** 2
+        steps = -(-T // 32)
+        work += F * G * steps
+        sps = min(info.chunk_steps, steps)
+        splits = -(-steps // sps)
+        items += F * G * splits
+    assert info.items == items
+    assert info.chunk_steps == max(32, work // (4 * 256))
+    assert 256 * 3 <= info.items <= 256 * 6
+    # an explicit chunk length
+    info2 = xe.batch_query(shapes, n_cu=256, chunk_steps=2 * info.chunk_steps)
+    assert info2.chunk_steps == 2 * info.chunk_steps and info2.items < info.items
+    # N not a multiple of 4 or an unaligned frame: a plain launch
+    info3 = xe.batch_query([(18, 2, 1000, 256), (64, 1, 4096, 256), (64, 1, 4096, 256)],
+                           aligned=[True, True, False])
+    assert (info3.instances, info3.unaligned) == (1, 2)
+    # partial sums of every chunked (channel, group) must fit the workspace
+    with pytest.raises(xe.XEngineError):
+        xe.batch_query([(4096, 64, 1 << 20, 256)], chunk_steps=32)
+    assert xe.batch_query([], n_cu=256).items == 0
 
 
 def test_create_without_gpu_is_clean(L):
@@ -113,27 +164,27 @@ def test_plan_query_shapes():
 
 
 def test_tile_groups_cover_the_triangle_once():
-    """Host model of the tile decomposition (eight waves per group): every
+    """Host model of the tile decomposition (four waves per group): every
     (I <= J) block pair of the triangle is owned by exactly one tile of one
-    wave of one group, for many N, and every wave has 16 MFMAs per step."""
+    wave of one group, for many N, and every wave runs 32 MFMAs per step
+    (a diagonal tile is one chain, an off-diagonal tile two)."""
     def groups(nb):
         ns = -(-nb // 8)
         out = []
         for gid in range(ns * ns):
             if gid < ns:
                 slots = [8 * gid + s for s in range(8)]
-                for w in range(8):
-                    tiles, mfmas = [], 0
-                    if w < 4:
-                        tiles += [(w, w + 1 + k) for k in range(4)]
-                        mfmas = 2 * 4
-                    else:
-                        p = w - 4
-                        tiles += [(p, p), (7 - p, 7 - p)]
-                        tiles += [(p, p + 5 + k) for k in range(3 - p)]
-                        tiles += [(7 - p, 8 - p + k) for k in range(p)]
-                        mfmas = 2 + 2 * 3
-                    assert mfmas == 8 and len(set(tiles)) == len(tiles)
+                for w in range(4):
+                    if w < 2:      # rows 2w, 2w+1 x columns 4..7
+                        tiles = [(2 * w + r, 4 + c) for r in range(2) for c in range(4)]
+                        mfmas = 2 * 2 * len(tiles)
+                    else:          # triangle of blocks b..b+3
+                        b = 4 * (w - 2)
+                        q = [(b + k, b + k) for k in range(4)]
+                        o = [(b + r, b + c) for r in range(4) for c in range(r + 1, 4)]
+                        tiles = q + o
+                        mfmas = 2 * len(q) + 2 * 2 * len(o)
+                    assert mfmas == 32 and len(set(tiles)) == len(tiles)
                     out += [(slots[r], slots[c]) for r, c in tiles]
             else:
                 q = gid - ns
@@ -144,9 +195,11 @@ def test_tile_groups_cover_the_triangle_once():
                     R += 1
                 C = R + 1 + p
                 slots = [8 * R + 4 * half + s for s in range(4)] + [8 * C + s for s in range(8)]
-                for w in range(8):
+                for w in range(4):
                     c0 = 4 + 4 * (w % 2)
-                    out += [(slots[w // 2], slots[c0 + k]) for k in range(4)]
+                    tiles = [(2 * (w // 2) + r, c0 + c) for r in range(2) for c in range(4)]
+                    assert 2 * 2 * len(tiles) == 32
+                    out += [(slots[r], slots[c]) for r, c in tiles]
         return out
     for nb in (1, 2, 3, 7, 8, 9, 15, 16, 17, 33, 64, 128):
         allt = groups(nb)

@@ -1,0 +1,189 @@
+"""Batched persistent launch vs the oracle and vs per-instance launches (GPU).
+
+Uneven instances (N from 64 to 1024, integration lengths spread over a
+factor of 64, own loss fractions) run as one persistent launch; each
+instance's integer sums must equal the oracle's and those of its own plain
+launch bit for bit, whatever else shares the launch.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_06189_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def xe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_06189_amd import xengine
+    xengine.lib()
+    return xengine
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+class Inst:
+    """Device copies of one instance's frame plus its own accumulators."""
+
+    def __init__(self, xe, fr):
+        self.fr = fr
+        self.packed = _dev(fr.packed)
+        self.mask = _dev(fr.mask) if fr.mask is not None else None
+        self.vis, self.cnt = xe.new_accumulators(fr.N, fr.F, self.packed.device)
+
+    def item(self):
+        return (self.packed, self.mask, self.fr.B, self.vis, self.cnt)
+
+    def zero(self):
+        self.vis.zero_()
+        self.cnt.zero_()
+
+
+def _frames(n_inst, t_scale, n_choices, seed=synth.SEEDS["batched"]):
+    specs = synth.batched_specs(seed, n_inst, t_scale, n_choices)
+    return [synth.instance_frame(s) for s in specs]
+
+
+def _check_oracle(orc, insts, times=1):
+    for k, ins in enumerate(insts):
+        fr = ins.fr
+        ev, en = orc.correlate(fr.packed, fr.mask, fr.B)
+        got_v = ins.vis.cpu().numpy().astype(np.int64)
+        got_n = ins.cnt.cpu().numpy()
+        assert np.array_equal(got_n, times * en), f"instance {k} ({fr.name}) counts"
+        assert np.array_equal(got_v, times * ev), f"instance {k} ({fr.name}) vis"
+
+
+def test_batch_matches_oracle(xe, orc):
+    frs = _frames(24, 0.08, (64, 128, 256, 512))
+    _say("batch vs oracle: " + " ".join(f.name for f in frs))
+    insts = [Inst(xe, f) for f in frs]
+    xe.accumulate_batch([i.item() for i in insts])
+    torch.cuda.synchronize()
+    _check_oracle(orc, insts)
+
+
+def test_batch_with_large_n_and_unaligned(xe, orc):
+    # N=1024 (16 groups), N not a multiple of 4 (plain launch), a one-sample
+    # instance, an instance with no mask, and an instance whose frame starts
+    # at an odd address (plain launch)
+    frs = [synth.instance_frame(synth.InstanceSpec(1024, 700, 2.5, 0.03, 11)),
+           synth.instance_frame(synth.InstanceSpec(18, 3000, 2.0, 0.05, 12)),
+           synth.instance_frame(synth.InstanceSpec(64, 1, 2.0, 0.0, 13)),
+           synth.gaussian_frame(14, 100, 3, 2049, 256, 2.5, 0.0),
+           synth.instance_frame(synth.InstanceSpec(256, 5000, 3.0, 0.02, 15))]
+    assert frs[3].mask is None
+    _say("batch edge cases: " + " ".join(f"N={f.N},F={f.F},T={f.T}" for f in frs))
+    insts = [Inst(xe, f) for f in frs]
+    # odd base address for the last instance's frame
+    big = torch.empty(frs[4].packed.size + 1, dtype=torch.uint8, device="cuda")
+    big[1:].copy_(insts[4].packed.reshape(-1))
+    insts[4].packed = big[1:].view(insts[4].packed.shape)
+    info = xe.batch_query([(f.N, f.F, f.T, f.B) for f in frs],
+                          aligned=[True, True, True, True, False])
+    assert info.unaligned == 2
+    xe.accumulate_batch([i.item() for i in insts])
+    torch.cuda.synchronize()
+    _check_oracle(orc, insts)
+
+
+def test_batch_equals_plain_launches_full_size(xe, orc):
+    """128 uneven instances at full size: the batch equals the instances'
+    own plain launches bit for bit."""
+    frs = synth.batched()
+    _say(f"batch vs plain launches: {len(frs)} instances, "
+         f"{sum(f.packed.size for f in frs) / 1e6:.0f} MB")
+    insts = [Inst(xe, f) for f in frs]
+    for ins in insts:
+        xe.accumulate(*ins.item())
+    torch.cuda.synchronize()
+    want = [(i.vis.clone(), i.cnt.clone()) for i in insts]
+    for ins in insts:
+        ins.zero()
+    xe.accumulate_batch([i.item() for i in insts])
+    torch.cuda.synchronize()
+    for k, (ins, (v, n)) in enumerate(zip(insts, want)):
+        assert torch.equal(ins.cnt, n), f"instance {k} counts"
+        assert torch.equal(ins.vis, v), f"instance {k} ({ins.fr.name}) vis"
+        fr = ins.fr
+        assert int(n[0].item()) == int(orc.valid_counts(fr.mask, fr.F, fr.T, fr.B)[0])
+
+
+def test_batch_ring_reuse(xe, orc):
+    """More calls than staging slots: every call accumulates once."""
+    frs = _frames(6, 0.05, (64, 128, 256))
+    insts = [Inst(xe, f) for f in frs]
+    reps = 7
+    for _ in range(reps):
+        xe.accumulate_batch([i.item() for i in insts])
+    torch.cuda.synchronize()
+    _check_oracle(orc, insts, times=reps)
+
+
+@pytest.mark.parametrize("chunk_steps", [0, 8, 100000])
+def test_batch_plan_replay_and_graph(xe, orc, chunk_steps):
+    """A plan run eagerly and from a captured graph, several replays with
+    eager work in between: each replay adds exactly one integration."""
+    frs = _frames(10, 0.06, (64, 128, 256, 512), seed=synth.SEEDS["batched"] + 1)
+    insts = [Inst(xe, f) for f in frs]
+    plan = xe.BatchPlan([i.item() for i in insts], chunk_steps=chunk_steps)
+    try:
+        plan.run()
+        torch.cuda.synchronize()
+        _check_oracle(orc, insts, times=1)
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                plan.run()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        # capture does not execute: still one integration
+        _check_oracle(orc, insts, times=1)
+        for rep in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            scratch = torch.ones(1 << 20, device="cuda").sum()  # eager work between
+            torch.cuda.synchronize()
+            assert scratch.item() == float(1 << 20)
+            _say(f"graph replay {rep} chunk_steps={chunk_steps}")
+            _check_oracle(orc, insts, times=2 + rep)
+        del g
+    finally:
+        plan.release()
+
+
+def test_batch_plan_slots(xe):
+    frs = _frames(2, 0.02, (64,))
+    insts = [Inst(xe, f) for f in frs]
+    h = xe.Handle(torch.cuda.current_device())
+    plans = [xe.BatchPlan([i.item() for i in insts], handle=h) for _ in range(4)]
+    with pytest.raises(xe.XEngineError):
+        xe.BatchPlan([i.item() for i in insts], handle=h)
+    plans[1].release()
+    p = xe.BatchPlan([i.item() for i in insts], handle=h)
+    p.release()
+    for q in plans:
+        q.release()
+    h.close()

@@ -1,0 +1,122 @@
+"""Streaming server on the GPU: results alone equal results in the mix,
+both equal the oracle, and a tight HBM budget delays frames without
+changing any result."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_06189_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def srv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_06189_amd import serve, xengine
+    xengine.lib()
+    return serve
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+@pytest.fixture(scope="module")
+def specs():
+    return synth.streaming_streams(n_streams=4, total_bps=4 * 2e9, T=1024,
+                                   n_choices=(64, 128), f_range=(2, 4), l_range=(2, 3),
+                                   max_loss=0.10)
+
+
+@pytest.fixture(scope="module")
+def pool(specs):
+    return {s.stream_id: [synth.stream_frame(s, k, 256) for k in range(2)] for s in specs}
+
+
+def _expected(orc, spec, pool, sequence, index):
+    L = spec.frames_per_integration
+    vis = cnt = None
+    for k in sequence[index * L:(index + 1) * L]:
+        fr = pool[spec.stream_id][k]
+        v, n = orc.correlate(fr.packed, fr.mask, fr.B)
+        vis = v if vis is None else vis + v
+        cnt = n if cnt is None else cnt + n
+    return vis, cnt, orc.normalize(vis, cnt)
+
+
+def _by_stream(res):
+    return {sid: [(r.index, r.vis, r.count, r.out) for r in lst]
+            for sid, lst in res.server.results.items()}
+
+
+def test_mix_equals_alone_and_oracle(srv, orc, specs, pool):
+    n_int = 2
+    mix = srv.run_load(specs, integrations=n_int, speed=50.0, pool=pool)
+    _say(f"mix: {mix.stats}")
+    assert mix.stats["frames"] == sum(n_int * s.frames_per_integration for s in specs)
+    assert mix.stats["mean_batch"] > 1.0      # frames of several streams shared launches
+    got_mix = _by_stream(mix)
+    for s in specs:
+        alone = srv.run_load([s], integrations=n_int, speed=50.0, pool=pool)
+        got_alone = _by_stream(alone)[s.stream_id]
+        assert len(got_alone) == n_int and len(got_mix[s.stream_id]) == n_int
+        for (ia, va, ca, oa), (im, vm, cm, om) in zip(got_alone, got_mix[s.stream_id]):
+            assert ia == im
+            assert np.array_equal(va, vm) and np.array_equal(ca, cm)
+            assert np.array_equal(oa.view(np.uint32), om.view(np.uint32))
+        for idx, v, c, o in got_mix[s.stream_id]:
+            ev, en, eo = _expected(orc, s, pool, mix.sequence[s.stream_id], idx)
+            assert np.array_equal(c, en), f"stream {s.stream_id} integration {idx} counts"
+            assert np.array_equal(v.astype(np.int64), ev), f"stream {s.stream_id} vis"
+            np.testing.assert_allclose(o, eo, rtol=1e-6, atol=0)
+
+
+def test_tight_budget_delays_but_does_not_change(srv, specs, pool):
+    from paper_1503_06189_amd.serve import StreamConfig, _Stream, frame_bytes
+    cfgs = [StreamConfig(s.stream_id, s.N, s.F, s.T, 256, s.frames_per_integration)
+            for s in specs]
+    resident = sum(_Stream.resident_bytes_for(c) for c in cfgs)
+    budget = resident + max(frame_bytes(c) for c in cfgs)   # one frame at a time
+    free = srv.run_load(specs, integrations=1, speed=float("inf"), pool=pool)
+    tight = srv.run_load(specs, integrations=1, speed=float("inf"), pool=pool,
+                         hbm_budget=budget)
+    _say(f"tight: {tight.stats}")
+    assert tight.stats["hbm_peak_used"] <= budget
+    assert tight.stats["admission_waits"] > 0
+    a, b = _by_stream(free), _by_stream(tight)
+    for sid in a:
+        for (i1, v1, c1, o1), (i2, v2, c2, o2) in zip(a[sid], b[sid]):
+            assert i1 == i2 and np.array_equal(v1, v2) and np.array_equal(c1, c2)
+
+
+def test_budget_too_small_for_a_stream(srv, specs):
+    from paper_1503_06189_amd.serve import StreamConfig, StreamServer
+    s = specs[0]
+    server = StreamServer(hbm_budget=1 << 16)
+    with pytest.raises(MemoryError):
+        server.open(StreamConfig(s.stream_id, s.N, s.F, s.T, 256, s.frames_per_integration))
+
+
+def test_device_resident_beats_plain_launches(srv, specs, pool):
+    """Serving loop with frames already in HBM vs one plain launch per frame
+    (same frames, same order): both finish, batched is not slower."""
+    n = 12
+    res = srv.run_load(specs, frames_per_stream=n, speed=float("inf"), pool=pool,
+                       device_resident=True, hbm_budget=1 << 34, max_inflight=2)
+    plain = srv.run_plain(specs, pool, n)
+    _say(f"served {res.stats['gbps']:.1f} Gb/s vs plain {plain['gbps']:.1f} Gb/s")
+    assert res.stats["frames"] == n * len(specs)
+    assert res.stats["p50_ms"] is not None and res.stats["p50_ms"] <= res.stats["p99_ms"]
