@@ -12,7 +12,18 @@ Prints ONE JSON line.  Fields beyond the common ones:
   roofline      the correlation kernel against the int8 MFMA peak: the
                 algorithmic ops per launch (8 per channel, upper-triangle
                 pair and sample) over its average duration, timed with HIP
-                events on the stream it runs on
+                events on the stream it runs on; traffic = HBM bytes per
+                launch from the committed counter runs, when they were
+                taken on the current kernel source
+  batched       128 uneven single-channel instances (N 64..1024, 1024 to
+                65536 samples) in one persistent launch replayed from a
+                captured graph, against the same instances as plain
+                per-instance launches; results compared bit for bit
+  serving       8 streams of 4096-sample frames offered with Poisson
+                arrivals at 51.2 Gb/s in total from pinned host memory:
+                p50/p99 frame latency (arrival to accumulated); plus the
+                serving loop's sustained rate on device-resident frames
+                against one plain launch per frame
   cpu_baseline  the oracle (plain C loops) on a bounded sample of the same
                 frame, on this host's cores
 """
@@ -42,7 +53,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(per_launch_alg_bytes):
+def measured_traffic():
     """HBM bytes per launch from the committed rocprofv3 counter runs, if
     they were taken on the current kernel source; else None."""
     try:
@@ -85,6 +96,109 @@ def cpu_baseline(fr, target_s: float):
     }
 
 
+def _events(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def batched_leg(torch, reps: int):
+    """Uneven instances: one graph-replayed persistent launch vs plain
+    per-instance launches on the same stream."""
+    from paper_1503_06189_amd import synth, tune, xengine
+    dev = torch.device("cuda:0")
+    h = xengine.default_handle(0)
+    frs = synth.batched()
+    items = []
+    for f in frs:
+        p = torch.from_numpy(f.packed).to(dev)
+        m = torch.from_numpy(f.mask).to(dev)
+        v, c = xengine.new_accumulators(f.N, f.F, dev)
+        items.append((p, m, f.B, v, c))
+    ops = sum(8 * f.N * (f.N + 1) // 2 * f.F * f.T for f in frs)
+    bits = sum(8 * f.N * f.F * f.T for f in frs)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch, 2)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def plain():
+        for it in items:
+            xengine.accumulate(*it, handle=h, stream=stream)
+
+    chunk = tune.tune(items, handle=h)
+    plan = xengine.BatchPlan(items, chunk_steps=chunk, handle=h)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            plan.run()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    ms_plain = timed(plain)
+    ms_graph = timed(g.replay)
+    # exactness: one plain pass and one batched pass from zero
+    for _, _, _, v, c in items:
+        v.zero_()
+        c.zero_()
+    plain()
+    torch.cuda.synchronize()
+    want = [(v.clone(), c.clone()) for _, _, _, v, c in items]
+    for _, _, _, v, c in items:
+        v.zero_()
+        c.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    exact = all(torch.equal(v, w) and torch.equal(c, n)
+                for (_, _, _, v, c), (w, n) in zip(items, want))
+    del g
+    plan.release()
+    return {
+        "workload": f"{len(frs)} uneven single-channel instances, N 64..1024, T 1024..65536",
+        "plain_ms": round(ms_plain, 4),
+        "batched_ms": round(ms_graph, 4),
+        "speedup": round(ms_plain / ms_graph, 2),
+        "gbps": round(bits / (ms_graph / 1e3) / 1e9, 1),
+        "plain_gbps": round(bits / (ms_plain / 1e3) / 1e9, 1),
+        "tops": round(ops / (ms_graph / 1e3) / 1e12, 1),
+        "mfma_frac": round(ops / (ms_graph / 1e3) / 1e12 / MFMA_INT8_PEAK_TOPS, 4),
+        "chunk_steps": chunk,
+        "exact_vs_plain": bool(exact),
+    }
+
+
+def serving_leg(torch, seconds: float):
+    from paper_1503_06189_amd import serve, synth
+    specs = synth.streaming_streams()
+    pool = serve._frame_pool(specs, 1, 256)
+    live = serve.run_load(specs, speed=1.0, duration=seconds, pool=pool, hbm_budget=2 << 30)
+    sat = serve.run_load(specs, frames_per_stream=12, speed=float("inf"), pool=pool,
+                         device_resident=True, hbm_budget=1 << 36)
+    plain = serve.run_plain(specs, pool, 12)
+    st = live.stats
+    return {
+        "workload": "8 streams, N in {128,256,512}, F 16..64, 4096-sample frames, "
+                    "Poisson arrivals, 51.2 Gb/s offered, Gilbert-Elliott loss",
+        "p50_ms": round(st["p50_ms"], 3),
+        "p99_ms": round(st["p99_ms"], 3),
+        "frames": st["frames"],
+        "offered_gbps": round(st["offered_gbps"], 1),
+        "sustained_gbps": round(st["gbps"], 1),
+        "mean_batch": round(st["mean_batch"], 2),
+        "hbm_budget_bytes": st["hbm_budget"],
+        "hbm_peak_used_bytes": st["hbm_peak_used"],
+        "device_resident_gbps": round(sat.stats["gbps"], 1),
+        "device_resident_plain_gbps": round(plain["gbps"], 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +206,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, copy 256 MiB once (a kernel of known "
+                         "traffic, to scale HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -131,10 +251,8 @@ def main():
     cnt.zero_()
     torch.cuda.synchronize()
 
-    k_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for _ in range(args.steps)]
-    s0 = torch.cuda.Event(enable_timing=True)
-    s1 = torch.cuda.Event(enable_timing=True)
+    k_ev = [tuple(_events(torch, 2)) for _ in range(args.steps)]
+    s0, s1 = _events(torch, 2)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     s0.record(stream)
@@ -155,8 +273,14 @@ def main():
     achieved_tops = ops / (kern_ms / 1e3) / 1e12
     alg_bytes = metrics.input_bytes(N, F, T) + 2 * metrics.output_bytes(N, F)
 
+    if args.copy_calibration:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
     res = {
-        "metric": "input Gb/s + int8 MFMA util at N=256x64ch",
+        "metric": "input Gb/s + int8 MFMA util at N=256x64ch; streaming p50/p99 frame latency",
         "value": round(value, 3),
         "unit": "Gb/s",
         "n_gpus": 1,
@@ -177,12 +301,19 @@ def main():
             "peak": MFMA_INT8_PEAK_TOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved_tops / MFMA_INT8_PEAK_TOPS, 4),
-            "traffic": measured_traffic(alg_bytes),
+            "traffic": measured_traffic(),
         },
         "kernel_ms": round(kern_ms, 5),
         "kernel_alg_hbm_gbps": round(alg_bytes / (kern_ms / 1e3) / 1e9, 1),
         "wall_s": round(t_wall, 4),
     }
+    del packed, mask, vis, cnt, out
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        res["batched"] = batched_leg(torch, reps=max(3, args.steps // 2))
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        res["serving"] = serving_leg(torch, args.serve_seconds)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(fr, args.cpu_seconds)
     print(json.dumps(res), flush=True)

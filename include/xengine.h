@@ -66,6 +66,7 @@ typedef int32_t xe_status;
 #define XE_ERR_NO_DEVICE (-7)   /* validation-only handle: nothing launched */
 
 #define XE_MAX_N 4096
+#define XE_MAX_FN 4194304       /* F * N per call (bytes per sample time)  */
 #define XE_MAX_SAMPLES 16777215 /* 128 * this < 2^31 */
 #define XE_DEVICE_NONE (-1)
 
@@ -92,7 +93,8 @@ const char *xe_last_error(xe_handle h);
 
 /* Correlate one frame and OVERWRITE vis and count with its sums
  * (Sec. II-B: correlation of a staged frame; Sec. II-C: the loss counter).
- * 1 <= N <= XE_MAX_N, F >= 1, 1 <= T <= XE_MAX_SAMPLES, B >= 1. */
+ * 1 <= N <= XE_MAX_N, F >= 1, F * N <= XE_MAX_FN, 1 <= T <= XE_MAX_SAMPLES,
+ * B >= 1. */
 xe_status xe_correlate_frame(xe_handle h, const uint8_t *packed,
                              const uint8_t *loss_mask, int32_t N, int32_t F,
                              int32_t T, int32_t B, int32_t *vis,

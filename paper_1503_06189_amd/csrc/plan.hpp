@@ -41,6 +41,24 @@ constexpr int kThreads = 64 * kWaves;
 // |Q| of a diagonal tile grows by at most 248 per sample: a chunk of at
 // most 2^18 steps (8,388,608 samples) keeps it inside int32
 constexpr int kMaxStepsPerChunk = 1 << 18;
+// Raw bytes are loaded this many steps ahead of their use; a chunk is run
+// in whole rings of kDepth steps (the last ring padded with zeros), so the
+// byte offsets of a chunk plus 2 * kDepth steps must stay below 2^31.
+#ifndef XE_DEPTH
+#define XE_DEPTH 4
+#endif
+constexpr int kDepth = XE_DEPTH;
+
+// longest chunk (in steps) whose byte offsets, lookahead included, stay
+// below 2^31 for F channels of N inputs
+inline int64_t max_steps_per_chunk(int64_t F, int64_t N) {
+    int64_t m = (((int64_t)1 << 31) - 1) / (F * N * kStep) - 2 * kDepth;
+    if (m > kMaxStepsPerChunk) m = kMaxStepsPerChunk;
+    return m - m % kDepth;
+}
+
+// round a chunk length up to whole rings
+inline int round_steps(int sps) { return (sps + kDepth - 1) / kDepth * kDepth; }
 
 // One tile group, in scalars (no arrays: kept in scalar registers on the
 // device).  Slot s of the staged blocks holds input block
@@ -112,7 +130,7 @@ inline void choose_split(int64_t units, int steps, int n_cu, int *splits,
     if (cap < 1) cap = 1;
     int64_t s = want < cap ? want : cap;
     if (s < 1) s = 1;
-    int sps = ceil_div(steps, (int)s);
+    int sps = round_steps(ceil_div(steps, (int)s));
     *steps_per_split = sps;
     *splits = ceil_div(steps, sps);
 }

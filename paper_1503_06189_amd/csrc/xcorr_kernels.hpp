@@ -190,6 +190,11 @@ __device__ __forceinline__ Chunk make_chunk(const CorrArgs &a, int f, int t_begi
     return c;
 }
 
+// The whole byte offset goes into the vector offset, which the hardware
+// checks against the resource's range (loads past the chunk read 0); the
+// scalar offset stays 0.  Offsets stay below 2^31 (the host bounds a
+// chunk, its lookahead included), so an inactive unit's 0x80000000 stays
+// out of range.
 template <bool kAligned, int UPT>
 __device__ __forceinline__ void issue_loads(const Chunk &ch, int tb, const Unit (&u)[UPT],
                                             Prefetch<UPT> &p) {
@@ -198,16 +203,15 @@ __device__ __forceinline__ void issue_loads(const Chunk &ch, int tb, const Unit 
     for (int r = 0; r < UPT; ++r) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int soff = (int)(step_off + (uint32_t)e * ch.row_bytes);
+            const uint32_t off = u[r].voff + step_off + (uint32_t)e * ch.row_bytes;
             if (kAligned) {
-                p.d[r][e] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(ch.rsrc, (int)u[r].voff,
-                                                                           soff, 0);
+                p.d[r][e] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(ch.rsrc, (int)off, 0, 0);
             } else {
                 uint32_t v = 0;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     uint32_t b = (uint8_t)__builtin_amdgcn_raw_buffer_load_b8(
-                        ch.rsrc, (int)(u[r].voff + c), soff, 0);
+                        ch.rsrc, (int)(off + c), 0, 0);
                     v |= (((u[r].inb >> c) & 1u) ? b : 0x88u) << (8 * c);
                 }
                 p.d[r][e] = v;
@@ -542,28 +546,42 @@ __device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int 
 #pragma unroll
     for (int k = 0; k < TL::NQ; ++k) acc.q[k] = (v16i){0};
 
-    // pipeline: loads run two steps ahead, decode one step ahead
+    // pipeline: a ring of kDepth register sets, set k holding the raw bytes
+    // of steps = k (mod kDepth).  Step s's loads are issued kDepth steps
+    // ahead (at iteration s - kDepth), decoded into LDS at iteration s - 1
+    // and multiplied at iteration s.  The loop is unrolled kDepth times so
+    // every set has fixed registers (no copies, which would wait for the
+    // loads in flight); steps past the chunk are staged as zeros.
+    // (the byte-load path needs more registers per set: a shallower ring)
+    constexpr int D = kAligned ? kDepth : 2;
+    static_assert(D % 2 == 0 && kDepth % D == 0,
+                  "the LDS double buffer alternates by step parity; chunks are whole rings");
     fill_mask_window(a, f, ch, 0, nsteps, mwords);
-    Prefetch<UPT> p_next, p_far;
-    issue_loads<kAligned>(ch, t_begin, u, p_next);
+    Prefetch<UPT> pf[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) issue_loads<kAligned>(ch, t_begin + k * kStep, u, pf[k]);
     __syncthreads();
-    commit<kDiagGroup>(u, p_next, __builtin_amdgcn_readfirstlane(mwords[0]), lds, SLOT);
-    issue_loads<kAligned>(ch, t_begin + kStep, u, p_next);
+    commit<kDiagGroup>(u, pf[0], __builtin_amdgcn_readfirstlane(mwords[0]), lds, SLOT);
     __syncthreads();
-    for (int s = 0; s < nsteps; ++s) {
-        uint8_t *cur = lds + (s & 1) * kBufBytes;
-        uint8_t *nxt = lds + ((s + 1) & 1) * kBufBytes;
-        if ((s + 1) % kMaskWindow == 0 && s + 1 < nsteps) {
-            // next window of validity words (uniform branch, rare)
-            fill_mask_window(a, f, ch, s + 1, nsteps, mwords);
+    const int npad = (nsteps + D - 1) / D * D;
+    for (int sb = 0; sb < npad; sb += D) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int s = sb + k;
+            uint8_t *cur = lds + (k & 1) * kBufBytes;
+            uint8_t *nxt = lds + ((k + 1) & 1) * kBufBytes;
+            if ((s + 1) % kMaskWindow == 0 && s + 1 < nsteps) {
+                // next window of validity words (uniform branch, rare)
+                fill_mask_window(a, f, ch, s + 1, nsteps, mwords);
+                __syncthreads();
+            }
+            const uint32_t vbits = s + 1 < nsteps
+                                       ? __builtin_amdgcn_readfirstlane(mwords[(s + 1) % kMaskWindow])
+                                       : 0u;
+            issue_loads<kAligned>(ch, t_begin + (s + D) * kStep, u, pf[k]);
+            fused_step<SHAPE, kDiagGroup>(cur, nxt, SLOT, s0, c0, acc, u, pf[(k + 1) % D], vbits);
             __syncthreads();
         }
-        const uint32_t vbits =
-            s + 1 < nsteps ? __builtin_amdgcn_readfirstlane(mwords[(s + 1) % kMaskWindow]) : 0u;
-        issue_loads<kAligned>(ch, t_begin + (s + 2) * kStep, u, p_far);
-        fused_step<SHAPE, kDiagGroup>(cur, nxt, SLOT, s0, c0, acc, u, p_next, vbits);
-        __syncthreads();
-        p_next = p_far;
     }
 
     // ---- epilogue, one tile at a time -----------------------------------

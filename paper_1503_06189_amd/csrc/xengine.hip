@@ -85,9 +85,10 @@ xe_status check_shape(xe_handle h, int32_t N, int32_t F, int32_t T, int32_t B) {
     int64_t P = (int64_t)N * (N + 1) / 2;
     if ((int64_t)F * P * 2 > ((int64_t)1 << 40)) return fail(h, XE_ERR_ARG, "F*P too large");
     if ((int64_t)T * F * N > ((int64_t)1 << 40)) return fail(h, XE_ERR_ARG, "frame too large");
-    // a staged step of 32 samples must stay addressable with 32-bit offsets
-    if ((int64_t)F * N * xe::kStep >= ((int64_t)1 << 30))
-        return fail(h, XE_ERR_ARG, "F*N too large for one call");
+    // a chunk with its lookahead must stay addressable with 31-bit offsets
+    static_assert((int64_t)XE_MAX_FN * xe::kStep * (2 * xe::kDepth + 2) < ((int64_t)1 << 31),
+                  "XE_MAX_FN too large for the prefetch depth");
+    if ((int64_t)F * N > XE_MAX_FN) return fail(h, XE_ERR_ARG, "F*N exceeds XE_MAX_FN");
     return XE_OK;
 }
 
@@ -124,9 +125,7 @@ bool fill_plan(int32_t N, int32_t F, int32_t T, int32_t n_cu, size_t ws_bytes,
     xe::choose_split(keys, steps, n_cu, &splits, &sps);
     // Chunk limits: the byte offsets inside a chunk stay below 2^31, and a
     // diagonal tile's Q (at most 248 per sample) stays within int32.
-    const int64_t step_bytes = (int64_t)F * N * xe::kStep;
-    int64_t max_sps = (((int64_t)1 << 31) - 1) / step_bytes - 1;
-    if (max_sps > xe::kMaxStepsPerChunk) max_sps = xe::kMaxStepsPerChunk;
+    const int64_t max_sps = xe::max_steps_per_chunk(F, N);
     if (sps > max_sps) {
         sps = (int)max_sps;
         splits = xe::ceil_div(steps, sps);
@@ -134,7 +133,7 @@ bool fill_plan(int32_t N, int32_t F, int32_t T, int32_t n_cu, size_t ws_bytes,
     // fewer chunks when their partial sums do not fit the workspace
     while (splits > 1 && (keys > kMaxKeys || kCounterBytes + partial_bytes(keys, splits) > ws_bytes)) {
         int want = splits - 1;
-        int next = xe::ceil_div(steps, want);
+        int next = xe::round_steps(xe::ceil_div(steps, want));
         if (next > max_sps) break;  // cannot merge chunks any further
         sps = next;
         splits = xe::ceil_div(steps, sps);
@@ -261,11 +260,11 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
         const int nb = xe::ceil_div(x.N, xe::kBlk);
         const int G = xe::groups_per_channel(nb);
         const int steps = xe::ceil_div(x.T, xe::kStep);
-        int64_t max_sps = ((((int64_t)1 << 31) - 1) / ((int64_t)x.F * x.N * xe::kStep)) - 1;
-        max_sps = std::min<int64_t>(max_sps, xe::kMaxStepsPerChunk);
+        const int64_t max_sps = xe::max_steps_per_chunk(x.F, x.N);
         int sps = (int)std::min<int64_t>(std::min<int64_t>(chunk_steps, steps), max_sps);
         int splits = xe::ceil_div(steps, sps);
-        sps = xe::ceil_div(steps, splits);
+        sps = std::min<int>(xe::round_steps(xe::ceil_div(steps, splits)), (int)max_sps);
+        splits = xe::ceil_div(steps, sps);
         xe::BatchInstance b;
         b.packed = x.packed;
         b.mask = x.loss_mask;

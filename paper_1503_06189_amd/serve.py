@@ -375,6 +375,7 @@ def _frame_pool(specs, distinct: int, B: int):
 
 def run_load(specs, frames_per_stream: Optional[int] = None, integrations: int = 1,
              speed: float = 1.0, hbm_budget: int = 2 << 30, distinct: int = 2,
+             duration: Optional[float] = None,
              B: int = 256, device: int = 0, max_inflight: int = 2,
              device_resident: bool = False, seed: int = 0, pool=None,
              handle: Optional[xengine.Handle] = None) -> LoadResult:
@@ -382,7 +383,8 @@ def run_load(specs, frames_per_stream: Optional[int] = None, integrations: int =
     its rate (``speed`` = inf: all at once) and serve them.
 
     Each stream sends ``frames_per_stream`` frames (default: ``integrations``
-    whole integrations), cycling through ``distinct`` generated frames.
+    whole integrations; with ``duration``: as many as its rate offers in that
+    many seconds), cycling through ``distinct`` generated frames.
     ``device_resident``: the frames are already in HBM (no host link), to
     measure the serving loop's own sustained rate."""
     import torch
@@ -404,8 +406,11 @@ def run_load(specs, frames_per_stream: Optional[int] = None, integrations: int =
     arrivals = []
     sequence = {}
     for s in specs:
-        n = frames_per_stream or integrations * s.frames_per_integration
         rate = s.frame_rate * speed
+        if duration is not None and np.isfinite(rate):
+            n = max(1, int(round(rate * duration)))
+        else:
+            n = frames_per_stream or integrations * s.frames_per_integration
         gaps = (rng.exponential(1.0 / rate, n) if np.isfinite(rate) else np.zeros(n))
         t = np.cumsum(gaps)
         k_pool = len(tens[s.stream_id])
