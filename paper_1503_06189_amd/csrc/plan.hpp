@@ -35,8 +35,8 @@ constexpr int kBlk = 32;          // inputs per tile edge (one 32x32 MFMA)
 constexpr int kStep = 32;         // samples staged per step
 constexpr int kSuper = 8;         // tile blocks per super-block edge
 constexpr int kMaxSlots = 12;     // input blocks staged per workgroup
-constexpr int kTilesPerWave = 10; // (Re, Im) tiles a wave writes out, at most
-constexpr int kWaves = 4;
+constexpr int kTilesPerWave = 5;  // (Re, Im) tiles a wave writes out, at most
+constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
 // |Q| of a diagonal tile grows by at most 248 per sample: a chunk of at
 // most 2^18 steps (8,388,608 samples) keeps it inside int32

@@ -63,8 +63,7 @@ struct CorrArgs {
     const uint8_t *mask;  // may be null
     int32_t *vis;
     int64_t *count;
-    int32_t *partials;    // [F*groups][splits][kGroupPartial] when splits > 1
-    int32_t *counters;    // [F*groups], zero between launches
+    int32_t *partials;    // [F*groups][splits-1][kGroupPartial] when splits > 1
     int N, F, T, B;
     int nblk_mask;        // ceil(T / B)
     int nb;               // ceil(N / 32)
@@ -285,27 +284,42 @@ __device__ __forceinline__ void commit(const Unit (&u)[UPT], const Prefetch<UPT>
 // the tiles of one wave
 // ---------------------------------------------------------------------------
 
-// Two tile shapes (see plan.hpp):
-//   kRect: rows s0, s0+1 x columns c0 .. c0+3 (8 off-diagonal tiles);
-//   kTri:  the triangle of blocks s0 .. s0+3: 4 diagonal tiles (as Q) and
-//          the 6 pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3).
-enum Shape { kRect = 0, kTri = 1 };
+// Three tile shapes (see plan.hpp), 16 MFMAs per 32-sample step each:
+//   kRect: row block s0 x column blocks c0 .. c0+3 (4 off-diagonal tiles);
+//   kTriA: of the 4 blocks s0 .. s0+3, the diagonal tiles of blocks 0 and 1
+//          (as Q) and the pairs (0,1) (0,2) (0,3);
+//   kTriB: the diagonal tiles of blocks 2 and 3 and the pairs (1,2) (1,3)
+//          (2,3).
+enum Shape { kRect = 0, kTriA = 1, kTriB = 2 };
 
 template <int SHAPE>
 struct Tiles;
 
 template <>
 struct Tiles<kRect> {
-    static constexpr int NQ = 0, NO = 8, NT = 8;
-    __device__ static constexpr int row(int k) { return k / 4; }      // of the off tiles
-    __device__ static constexpr int col(int k) { return k % 4; }
+    static constexpr int NQ = 0, NO = 4, NT = 4, NXP = 1;
+    __device__ static constexpr int qb(int) { return 0; }
+    __device__ static constexpr int row(int) { return 0; }
+    __device__ static constexpr int col(int t) { return t; }
+    __device__ static constexpr int xpi(int) { return 0; }  // Xp index of a row
 };
 
 template <>
-struct Tiles<kTri> {
-    static constexpr int NQ = 4, NO = 6, NT = 10;
-    __device__ static constexpr int row(int k) { return k < 3 ? 0 : (k < 5 ? 1 : 2); }
-    __device__ static constexpr int col(int k) { return k < 3 ? k + 1 : (k < 5 ? k - 1 : 3); }
+struct Tiles<kTriA> {
+    static constexpr int NQ = 2, NO = 3, NT = 5, NXP = 1;
+    __device__ static constexpr int qb(int k) { return k; }
+    __device__ static constexpr int row(int) { return 0; }
+    __device__ static constexpr int col(int t) { return t + 1; }
+    __device__ static constexpr int xpi(int) { return 0; }
+};
+
+template <>
+struct Tiles<kTriB> {
+    static constexpr int NQ = 2, NO = 3, NT = 5, NXP = 2;
+    __device__ static constexpr int qb(int k) { return 2 + k; }
+    __device__ static constexpr int row(int t) { return t < 2 ? 1 : 2; }
+    __device__ static constexpr int col(int t) { return t < 2 ? t + 2 : 3; }
+    __device__ static constexpr int xpi(int i) { return i - 1; }
 };
 
 template <int SHAPE>
@@ -315,154 +329,200 @@ struct Acc {
     v16i re[T::NO], im[T::NO];
 };
 
-// MFMAs of one staged step.  Both sub-steps' operands are read first.
+// Operand fragments of one 16-sample sub-step.  kRect: x[0] = the row
+// block, y[j] = column block c0 + j.  kTriA/B: x[i] = block s0 + i (the
+// ones the shape uses), xs[k] = Xs of its k-th diagonal block.
 template <int SHAPE>
-__device__ __forceinline__ void compute_step(const uint8_t *buf, int slot_bytes, int s0, int c0,
-                                             Acc<SHAPE> &acc) {
+struct Ops {
+    static constexpr bool kTri = SHAPE != kRect;
+    v4i x[kTri ? 4 : 1];
+    v4i y[kTri ? 1 : 4];
+    v4i xs[kTri ? 2 : 1];
+};
+
+template <int SHAPE>
+__device__ __forceinline__ void read_ops(const uint8_t *buf, int slot_bytes, int s0, int c0,
+                                         int sub, Ops<SHAPE> &o) {
     const int lane = threadIdx.x & 63;
-    auto frag = [&](int s, int op, int sub) {
+    auto frag = [&](int s, int op) {
         return *(const v4i *)(buf + chunk_off(slot_bytes, s, op, sub, lane));
     };
     if (SHAPE == kRect) {
-        v4i x[2][2], y[2][4];
+        o.x[0] = frag(s0, 0);
 #pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i) x[sub][i] = frag(s0 + i, 0, sub);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) y[sub][j] = frag(c0 + j, 0, sub);
-        }
-#pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                v4i p = make_xp(x[sub][i]);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc.re[4 * i + j] = mfma(x[sub][i], y[sub][j], acc.re[4 * i + j]);
-                    acc.im[4 * i + j] = mfma(p, y[sub][j], acc.im[4 * i + j]);
-                }
-            }
-        }
+        for (int j = 0; j < 4; ++j) o.y[j] = frag(c0 + j, 0);
     } else {
-        v4i x[2][4], xs[2][4];
 #pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
+        for (int i = SHAPE == kTriA ? 0 : 1; i < 4; ++i) o.x[i] = frag(s0 + i, 0);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                x[sub][i] = frag(s0 + i, 0, sub);
-                xs[sub][i] = frag(s0 + i, 1, sub);
-            }
-        }
-#pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc.q[i] = mfma(xs[sub][i], x[sub][i], acc.q[i]);
-            v4i p[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) p[i] = make_xp(x[sub][i]);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const int i = Tiles<kTri>::row(k), j = Tiles<kTri>::col(k);
-                acc.re[k] = mfma(x[sub][i], x[sub][j], acc.re[k]);
-                acc.im[k] = mfma(p[i], x[sub][j], acc.im[k]);
-            }
-        }
+        for (int k = 0; k < 2; ++k) o.xs[k] = frag(s0 + Tiles<SHAPE>::qb(k), 1);
     }
 }
 
-// One loop step with the decode of the next step woven into the MFMA
-// stream.  The wave is alone on its SIMD, so it must itself keep the matrix
-// core busy while it decodes: the 32 MFMAs are issued in a fixed order and
-// after every few of them comes one small piece of the decode (a 4x4
-// transpose, or the decode and LDS write of one input), pinned in place by
-// scheduling barriers.  A piece's VALU work issues while the MFMA before it
-// occupies the matrix core.
+// One loop step: the 16 MFMAs of step s, with the decode of step s + 2
+// woven into them and the operands of the next sub-steps read ahead.
+//   * (s, sub 0) operands arrive in `o`, read during the previous step;
+//     (s, sub 1) operands are read at the start; (s + 1, sub 0) operands
+//     are read into `o` once the sub-0 MFMAs have taken theirs, so the next
+//     step starts its MFMAs as soon as it passes the barrier.
+//   * the decode of step s + 2 comes in small pieces (a 4x4 transpose, or
+//     the decode and LDS write of one input) between MFMAs, spread over the
+//     first 14 of them so the last LDS write lands before the barrier.  A
+//     piece's VALU work issues while the MFMA before it occupies the matrix
+//     core; scheduling barriers keep the order.
 template <int SHAPE, bool kXs, int UPT>
-__device__ __forceinline__ void fused_step(const uint8_t *cur, uint8_t *nxt, int slot_bytes,
-                                           int s0, int c0, Acc<SHAPE> &acc,
-                                           const Unit (&u)[UPT], const Prefetch<UPT> &p,
-                                           uint32_t vbits) {
-    constexpr int kPieces = 5 * UPT;  // per unit: transpose, 4 inputs
-    const int lane = threadIdx.x & 63;
-    auto frag = [&](int s, int op, int sub) {
-        return *(const v4i *)(cur + chunk_off(slot_bytes, s, op, sub, lane));
-    };
-    constexpr int NX = SHAPE == kRect ? 2 : 4;   // row operands
-    constexpr int NY = SHAPE == kRect ? 4 : 0;   // column operands (rectangles)
-    v4i x[2][NX], y[2][NY > 0 ? NY : 1], xs[2][SHAPE == kTri ? 4 : 1], xp[NX];
-    auto read_sub = [&](int sub) {
-#pragma unroll
-        for (int i = 0; i < NX; ++i) {
-            x[sub][i] = frag(s0 + i, 0, sub);
-            if (SHAPE == kTri) xs[sub][i] = frag(s0 + i, 1, sub);
-        }
-#pragma unroll
-        for (int j = 0; j < NY; ++j) y[sub][j] = frag(c0 + j, 0, sub);
-    };
+__device__ __forceinline__ void pipelined_step(const uint8_t *cur, const uint8_t *next,
+                                               uint8_t *dec, int slot_bytes, int s0, int c0,
+                                               Acc<SHAPE> &acc, const Unit (&u)[UPT],
+                                               const Prefetch<UPT> &p, uint32_t vbits,
+                                               Ops<SHAPE> &o) {
+    // 5 pieces: the transposes of all units, then input c of all units;
+    // the units' chains are independent, so a piece has UPT-fold ILP
+    constexpr int kPieces = 5;
+    constexpr int kSpan = 14;
+    using TL = Tiles<SHAPE>;
+    Ops<SHAPE> o1;
+    read_ops(cur, slot_bytes, s0, c0, 1, o1);
     // decode state
     uint32_t L[UPT][4];
     uint32_t msk[UPT];
     auto piece = [&](int k) {
-        const int r = k / 5, c = k % 5 - 1;
+        const int c = k - 1;
         if (c < 0) {
-            transpose4(p.d[r], L[r]);
-            const uint32_t vq = u[r].act ? (vbits >> (4 * u[r].sq)) & 15u : 0u;
-            msk[r] = bits_to_bytes(vq);
+#pragma unroll
+            for (int r = 0; r < UPT; ++r) {
+                transpose4(p.d[r], L[r]);
+                const uint32_t vq = u[r].act ? (vbits >> (4 * u[r].sq)) & 15u : 0u;
+                msk[r] = bits_to_bytes(vq);
+            }
         } else {
-            const int o = u[r].sq >> 1, h = u[r].sq & 1;
-            uint32_t Lm = (L[r][c] & msk[r]) | (0x88888888u & ~msk[r]);
-            uint32_t an = (Lm >> 4) & 0x0f0f0f0fu, bn = Lm & 0x0f0f0f0fu;
-            uint8_t *dst = nxt + chunk_off(slot_bytes, u[r].s, 0, o >> 1,
-                                           (o & 1) * 32 + 4 * u[r].q + c) + 8 * h;
-            v2u xr = {nib_to_s8(an), nib_to_s8(bn)};
-            *(v2u *)dst = xr;
-            if (kXs) {
-                v2u v = {(an + bn + 0x70707070u) ^ 0x80808080u,
-                         ((bn | 0x80808080u) - an) ^ 0x80808080u};
-                *(v2u *)(dst + kFragBytes) = v;
+#pragma unroll
+            for (int r = 0; r < UPT; ++r) {
+                const int oo = u[r].sq >> 1, h = u[r].sq & 1;
+                uint32_t Lm = (L[r][c] & msk[r]) | (0x88888888u & ~msk[r]);
+                uint32_t an = (Lm >> 4) & 0x0f0f0f0fu, bn = Lm & 0x0f0f0f0fu;
+                uint8_t *dst = dec + chunk_off(slot_bytes, u[r].s, 0, oo >> 1,
+                                               (oo & 1) * 32 + 4 * u[r].q + c) + 8 * h;
+                v2u xr = {nib_to_s8(an), nib_to_s8(bn)};
+                *(v2u *)dst = xr;
+                if (kXs) {
+                    v2u v = {(an + bn + 0x70707070u) ^ 0x80808080u,
+                             ((bn | 0x80808080u) - an) ^ 0x80808080u};
+                    *(v2u *)(dst + kFragBytes) = v;
+                }
             }
         }
     };
-    // MFMA m of the step (m = 16 sub + op)
-    auto mfma_op = [&](int m) {
-        const int sub = m / 16, k = m % 16;
+    v4i xp[TL::NXP];
+    auto rows_xp = [&](const Ops<SHAPE> &q) {
         if (SHAPE == kRect) {
-            const int t = k / 2, i = t / 4, j = t % 4;
-            if (k % 2 == 0)
-                acc.re[t] = mfma(x[sub][i], y[sub][j], acc.re[t]);
-            else
-                acc.im[t] = mfma(xp[i], y[sub][j], acc.im[t]);
+            xp[0] = make_xp(q.x[0]);
         } else {
-            if (k < 4) {
-                acc.q[k] = mfma(xs[sub][k], x[sub][k], acc.q[k]);
-            } else {
-                const int t = (k - 4) / 2;
-                const int i = Tiles<kTri>::row(t), j = Tiles<kTri>::col(t);
-                if (k % 2 == 0)
-                    acc.re[t] = mfma(x[sub][i], x[sub][j], acc.re[t]);
-                else
-                    acc.im[t] = mfma(xp[i], x[sub][j], acc.im[t]);
-            }
+#pragma unroll
+            for (int i = 0; i < TL::NXP; ++i) xp[i] = make_xp(q.x[TL::row(2 * i)]);
+        }
+    };
+    // MFMA k (0..7) of a sub-step
+    auto mfma_op = [&](const Ops<SHAPE> &q, int k) {
+        if (SHAPE == kRect) {
+            const int t = k / 2;
+            if (k % 2 == 0)
+                acc.re[t] = mfma(q.x[0], q.y[t], acc.re[t]);
+            else
+                acc.im[t] = mfma(xp[0], q.y[t], acc.im[t]);
+        } else if (k < 2) {
+            acc.q[k] = mfma(q.xs[k], q.x[TL::qb(k)], acc.q[k]);
+        } else {
+            const int t = (k - 2) / 2;
+            const int i = TL::row(t), j = TL::col(t);
+            if (k % 2 == 0)
+                acc.re[t] = mfma(q.x[i], q.x[j], acc.re[t]);
+            else
+                acc.im[t] = mfma(xp[TL::xpi(i)], q.x[j], acc.im[t]);
         }
     };
 
-    read_sub(0);
-    read_sub(1);
+    rows_xp(o);
 #pragma unroll
-    for (int m = 0; m < 32; ++m) {
-        if (m % 16 == 0) {
+    for (int m = 0; m < 16; ++m) {
+        if (m == 8) rows_xp(o1);
+        if (m == 9) read_ops(next, slot_bytes, s0, c0, 0, o);
+        if (m < 8)
+            mfma_op(o, m);
+        else
+            mfma_op(o1, m - 8);
 #pragma unroll
-            for (int i = 0; i < NX; ++i) xp[i] = make_xp(x[m / 16][i]);
-        }
-        mfma_op(m);
-        // pieces spread evenly over the 32 MFMAs
-        constexpr int kStride = 32 / kPieces > 0 ? 32 / kPieces : 1;
-        if (m % kStride == kStride - 1 && m / kStride < kPieces) piece(m / kStride);
+        for (int q = 0; q < kPieces; ++q)
+            if (q * kSpan / kPieces == m) piece(q);
         __builtin_amdgcn_sched_barrier(0);
     }
-#pragma unroll
-    for (int k = 32 / (32 / kPieces > 0 ? 32 / kPieces : 1); k < kPieces; ++k) piece(k);
+}
+
+// Where the tiles of a wave lie: tile k < NQ is the diagonal tile of block
+// qb(k), the others pair a row block with a column block.  Element v of a
+// tile held by `lane` is (i, j) = (8 (v/4) + 4 (lane/32) + v%4, lane%32)
+// within the tile (the output layout of v_mfma_i32_32x32x32_i8).
+template <int SHAPE>
+struct TileMap {
+    Group g;
+    int s0, c0, N;
+    __device__ void rc(int k, int &rs, int &cs) const {
+        using TL = Tiles<SHAPE>;
+        if (k < TL::NQ) {
+            rs = cs = s0 + TL::qb(k);
+        } else if (SHAPE == kRect) {
+            rs = s0;
+            cs = c0 + TL::col(k - TL::NQ);
+        } else {
+            rs = s0 + TL::row(k - TL::NQ);
+            cs = s0 + TL::col(k - TL::NQ);
+        }
+    }
+    // index of the element in the packed triangle, or -1 when it lies below
+    // the diagonal or past N
+    __device__ int64_t elem(int k, int v, int lane) const {
+        int rs, cs;
+        rc(k, rs, cs);
+        const int i = slot_block(g, rs) * kBlk + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int j = slot_block(g, cs) * kBlk + (lane & 31);
+        if (i > j || j >= N) return -1;
+        return (int64_t)i * N - (int64_t)i * (i - 1) / 2 + (j - i);
+    }
+};
+
+// The role of wave `wave` in a tile group: its staging share, tile shape and
+// first row / column slot.  Waves w and w + 4 share a SIMD: each SIMD gets
+// one rectangle and (diagonal group) one half triangle.
+template <int NSLOT_, int SHAPE_, int UPT_>
+struct Role {
+    static constexpr int NSLOT = NSLOT_, SHAPE = SHAPE_, UPT = UPT_;
+};
+
+template <class Fn>
+__device__ __forceinline__ void with_role(const Group &g, int wave, Fn &&fn) {
+    if (g.diag) {
+        if (wave < 4)  // row block `wave` x columns 4..7
+            fn(Role<8, kRect, 1>{}, wave, 4);
+        else if ((wave & 1) == 0)  // triangle of blocks 0..3 (wave 4) or 4..7 (wave 6)
+            fn(Role<8, kTriA, 1>{}, 2 * (wave - 4), 0);
+        else
+            fn(Role<8, kTriB, 1>{}, 2 * (wave - 5), 0);
+    } else {
+        // row slot wave % 4 x column slots 4 + 4 (wave / 4) .. + 3
+        if (wave < 4)
+            fn(Role<12, kRect, 2>{}, wave, 4);
+        else
+            fn(Role<12, kRect, 1>{}, wave - 4, 8);
+    }
+}
+
+// (Re, Im) partial tiles of chunk `split` (>= 1) of tile group `key`, wave
+// `wave`: [tile k][re 0..3 | im 4..7][lane] x 4 int32
+template <class T>
+__device__ __forceinline__ T *partial_tiles(T *partials, int64_t key, int splits, int split,
+                                            int wave) {
+    return partials + (key * (splits - 1) + (split - 1)) * kGroupPartial +
+           (int64_t)wave * kWavePartial;
 }
 
 // valid samples of channel f in [t0, t1)
@@ -502,12 +562,14 @@ __device__ __forceinline__ void split_q(const v16i &q, int32_t *tbuf, v16i &re, 
     __builtin_amdgcn_wave_barrier();
 }
 
-template <bool kAligned, bool kOverwrite, int NSLOT, int SHAPE>
+// UPT = staging units per lane and step (wave-rounds of 64 units): the
+// 16 (diagonal) or 24 (off-diagonal) wave-rounds of a step are dealt to the
+// 8 waves as x = r * 8 + wave.
+template <bool kAligned, bool kOverwrite, int NSLOT, int SHAPE, int UPT>
 __device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int f, int gid,
                                          int split, int s0, int c0, uint8_t *lds,
-                                         uint32_t *mwords, int *s_flag) {
+                                         uint32_t *mwords) {
     using TL = Tiles<SHAPE>;
-    constexpr int UPT = NSLOT / 4;     // wave-rounds of 64 units per wave
     constexpr bool kDiagGroup = NSLOT == 8;
     constexpr int SLOT = kDiagGroup ? 2 * kFragBytes : kFragBytes;
     const int wave = threadIdx.x >> 6;
@@ -546,63 +608,67 @@ __device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int 
 #pragma unroll
     for (int k = 0; k < TL::NQ; ++k) acc.q[k] = (v16i){0};
 
-    // pipeline: a ring of kDepth register sets, set k holding the raw bytes
-    // of steps = k (mod kDepth).  Step s's loads are issued kDepth steps
-    // ahead (at iteration s - kDepth), decoded into LDS at iteration s - 1
-    // and multiplied at iteration s.  The loop is unrolled kDepth times so
-    // every set has fixed registers (no copies, which would wait for the
-    // loads in flight); steps past the chunk are staged as zeros.
-    // (the byte-load path needs more registers per set: a shallower ring)
-    constexpr int D = kAligned ? kDepth : 2;
-    static_assert(D % 2 == 0 && kDepth % D == 0,
-                  "the LDS double buffer alternates by step parity; chunks are whole rings");
+    // pipeline, per step s:
+    //   raw bytes   loaded kDepth steps ahead into a ring of register sets
+    //               (set k holds steps = k mod D), loop unrolled D times so
+    //               each set has fixed registers;
+    //   decode      two steps ahead, into the third of three LDS buffers;
+    //   MFMA        from the buffer of step s, operands read ahead.
+    // Steps past the chunk are staged as zeros (the last ring is padded).
+    constexpr int D = kAligned ? kDepth : 3;
+    static_assert(D >= 3, "the ring must hold the step being decoded and two in flight");
+    // validity words: a window of kMaskWindow steps in LDS; each lane caches
+    // the word of one of the next 64 steps, read out with readlane
     fill_mask_window(a, f, ch, 0, nsteps, mwords);
     Prefetch<UPT> pf[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) issue_loads<kAligned>(ch, t_begin + k * kStep, u, pf[k]);
     __syncthreads();
-    commit<kDiagGroup>(u, pf[0], __builtin_amdgcn_readfirstlane(mwords[0]), lds, SLOT);
+    uint32_t mcache = mwords[lane];
+    auto vbits_of = [&](int j) -> uint32_t {
+        return j < nsteps ? (uint32_t)__builtin_amdgcn_readlane((int)mcache, j & 63) : 0u;
+    };
+    commit<kDiagGroup>(u, pf[0], vbits_of(0), lds, SLOT);
+    commit<kDiagGroup>(u, pf[1], vbits_of(1), lds + kBufBytes, SLOT);
     __syncthreads();
+    Ops<SHAPE> ops;
+    read_ops(lds, SLOT, s0, c0, 0, ops);
+    int b_cur = 0, b_next = kBufBytes, b_dec = 2 * kBufBytes;  // LDS byte offsets
     const int npad = (nsteps + D - 1) / D * D;
     for (int sb = 0; sb < npad; sb += D) {
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const int s = sb + k;
-            uint8_t *cur = lds + (k & 1) * kBufBytes;
-            uint8_t *nxt = lds + ((k + 1) & 1) * kBufBytes;
-            if ((s + 1) % kMaskWindow == 0 && s + 1 < nsteps) {
-                // next window of validity words (uniform branch, rare)
-                fill_mask_window(a, f, ch, s + 1, nsteps, mwords);
-                __syncthreads();
+            const int j = s + 2;  // step decoded now
+            if ((j & 63) == 0 && j < nsteps) {
+                if (j % kMaskWindow == 0) {
+                    // next window of validity words (uniform branch, rare)
+                    fill_mask_window(a, f, ch, j, nsteps, mwords);
+                    __syncthreads();
+                }
+                mcache = mwords[(j % kMaskWindow) + lane];
             }
-            const uint32_t vbits = s + 1 < nsteps
-                                       ? __builtin_amdgcn_readfirstlane(mwords[(s + 1) % kMaskWindow])
-                                       : 0u;
+            const uint32_t vbits = vbits_of(j);
             issue_loads<kAligned>(ch, t_begin + (s + D) * kStep, u, pf[k]);
-            fused_step<SHAPE, kDiagGroup>(cur, nxt, SLOT, s0, c0, acc, u, pf[(k + 1) % D], vbits);
+            pipelined_step<SHAPE, kDiagGroup>(lds + b_cur, lds + b_next, lds + b_dec, SLOT, s0,
+                                              c0, acc, u, pf[(k + 2) % D], vbits, ops);
             __syncthreads();
+            const int t = b_cur;
+            b_cur = b_next;
+            b_next = b_dec;
+            b_dec = t;
         }
     }
 
     // ---- epilogue, one tile at a time -----------------------------------
-    // tiles of this wave: k < NQ diagonal, then the off-diagonal ones
+    // Chunk 0 (or the only chunk) writes the sums: plain stores (overwrite)
+    // or read-add-write (accumulate).  Later chunks store their tiles in the
+    // workspace and the merge kernel, launched next on the same stream, adds
+    // them: the kernel boundary orders the two, so no fence or counter is
+    // needed and the additions spread over the whole GPU.
     constexpr int NT = TL::NT;
     int32_t *tbuf = (int32_t *)lds + wave * (32 * 33);  // staging buffers are free now
-    const int64_t key = (int64_t)f * a.groups + gid;
-    const int64_t P = (int64_t)a.N * (a.N + 1) / 2;
-    int32_t *visf = a.vis + (int64_t)f * P * 2;
-
-    auto tile_rc = [&](int k, int &rs, int &cs) {
-        if (k < TL::NQ) {
-            rs = cs = s0 + k;
-        } else if (SHAPE == kRect) {
-            rs = s0 + TL::row(k - TL::NQ);
-            cs = c0 + TL::col(k - TL::NQ);
-        } else {
-            rs = s0 + TL::row(k - TL::NQ);
-            cs = s0 + TL::col(k - TL::NQ);
-        }
-    };
+    const TileMap<SHAPE> map{g, s0, c0, a.N};
     auto tile = [&](int k, v16i &re, v16i &im) {
         if (k < TL::NQ) {
             split_q(acc.q[k < TL::NQ ? k : 0], tbuf, re, im);
@@ -611,53 +677,9 @@ __device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int 
             im = acc.im[k - TL::NQ];
         }
     };
-    // element v of tile k held by this lane: its index in the packed
-    // triangle, or -1 when it lies below the diagonal or past N
-    auto elem = [&](int k, int v) -> int64_t {
-        int rs, cs;
-        tile_rc(k, rs, cs);
-        int i = slot_block(g, rs) * kBlk + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        int j = slot_block(g, cs) * kBlk + (lane & 31);
-        if (i > j || j >= a.N) return -1;
-        return (int64_t)i * a.N - (int64_t)i * (i - 1) / 2 + (j - i);
-    };
-    // previous contents of tile k (accumulate mode), all loads issued
-    // before any store of the tile so they overlap
-    auto load_old = [&](int k, v2i (&old)[16]) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            int64_t idx = elem(k, v);
-            old[v] = idx >= 0 ? *(const v2i *)(visf + 2 * idx) : (v2i){0, 0};
-        }
-    };
-    auto store = [&](int k, const v16i &re, const v16i &im, const v2i (&old)[16]) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            int64_t idx = elem(k, v);
-            if (idx >= 0) {
-                v2i val = {re[v], im[v]};
-                *(v2i *)(visf + 2 * idx) = kOverwrite ? val : old[v] + val;
-            }
-        }
-    };
-    // partial layout per wave: [tile k][re 0..3 | im 4..7][lane] x 4 int32
-    auto part = [&](int sp) {
-        return a.partials + (key * a.splits + sp) * kGroupPartial + (int64_t)wave * kWavePartial;
-    };
-
-    v2i old[16];
-    if (a.splits == 1) {
-#pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            if (!kOverwrite) load_old(k, old);
-            v16i re, im;
-            tile(k, re, im);
-            store(k, re, im, old);
-        }
-    } else {
-        // merge time chunks: everyone writes its tiles; the last to arrive
-        // sums all of them
-        int32_t *mine = part(split);
+    if (split > 0) {
+        const int64_t key = (int64_t)f * a.groups + gid;
+        int32_t *mine = partial_tiles(a.partials, key, a.splits, split, wave);
 #pragma unroll
         for (int k = 0; k < NT; ++k) {
             v16i re, im;
@@ -670,35 +692,31 @@ __device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int 
                 *(v4i *)(mine + ((k * 8 + 4 + v) * 64 + lane) * 4) = y;
             }
         }
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int old_count = atomicAdd(&a.counters[key], 1);
-            *s_flag = (old_count == a.splits - 1);
-        }
-        __syncthreads();
-        if (!*s_flag) return;
-        __threadfence();
+        return;
+    }
+    const int64_t P = (int64_t)a.N * (a.N + 1) / 2;
+    int32_t *visf = a.vis + (int64_t)f * P * 2;
 #pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            if (!kOverwrite) load_old(k, old);
-            v16i re = (v16i){0}, im = (v16i){0};
-            for (int sp = 0; sp < a.splits; ++sp) {
-                const int32_t *src = part(sp);
+    for (int k = 0; k < NT; ++k) {
+        // previous contents first (accumulate), all loads before any store
+        v2i old[16];
+        if (!kOverwrite) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    v4i x = *(const v4i *)(src + ((k * 8 + v) * 64 + lane) * 4);
-                    v4i y = *(const v4i *)(src + ((k * 8 + 4 + v) * 64 + lane) * 4);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        re[4 * v + c] += x[c];
-                        im[4 * v + c] += y[c];
-                    }
-                }
+            for (int v = 0; v < 16; ++v) {
+                const int64_t idx = map.elem(k, v, lane);
+                old[v] = idx >= 0 ? *(const v2i *)(visf + 2 * idx) : (v2i){0, 0};
             }
-            store(k, re, im, old);
         }
-        if (threadIdx.x == 0) a.counters[key] = 0;  // ready for the next launch
+        v16i re, im;
+        tile(k, re, im);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int64_t idx = map.elem(k, v, lane);
+            if (idx >= 0) {
+                v2i val = {re[v], im[v]};
+                *(v2i *)(visf + 2 * idx) = kOverwrite ? val : old[v] + val;
+            }
+        }
     }
     if (gid == 0 && threadIdx.x == 0) {
         int64_t n = valid_count(a, f, 0, a.T);
@@ -720,30 +738,22 @@ __device__ __forceinline__ int64_t xcd_local_index(int64_t b, int64_t total) {
 // fixed per group kind (blocks past N are staged as zeros).
 template <bool kAligned, bool kOverwrite>
 __device__ __forceinline__ void run_item(const CorrArgs &a, int f, int gid, int split,
-                                         uint8_t *lds, uint32_t *mwords, int *s_flag) {
+                                         uint8_t *lds, uint32_t *mwords) {
     const Group g = make_group(a.nb, gid);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (g.diag) {
-        if (wave < 2)  // rows 2w, 2w+1 x columns 4..7
-            run_wave<kAligned, kOverwrite, 8, kRect>(a, g, f, gid, split, 2 * wave, 4, lds,
-                                                     mwords, s_flag);
-        else           // triangle of blocks 4(w-2) .. 4(w-2)+3
-            run_wave<kAligned, kOverwrite, 8, kTri>(a, g, f, gid, split, 4 * (wave - 2), 0, lds,
-                                                    mwords, s_flag);
-    } else {
-        // rows 2(w/2), 2(w/2)+1 x column slots 4 + 4(w%2) .. +3
-        run_wave<kAligned, kOverwrite, 12, kRect>(a, g, f, gid, split, 2 * (wave / 2),
-                                                  4 + 4 * (wave % 2), lds, mwords, s_flag);
-    }
+    with_role(g, wave, [&](auto role, int s0, int c0) {
+        using R = decltype(role);
+        run_wave<kAligned, kOverwrite, R::NSLOT, R::SHAPE, R::UPT>(a, g, f, gid, split, s0, c0,
+                                                                  lds, mwords);
+    });
 }
 
 // One frame: workgroup -> (channel, group, chunk), groups of a channel
 // and chunks of a (channel, group) numbered next to each other.
 template <bool kAligned, bool kOverwrite>
 __global__ __launch_bounds__(kThreads, 1) void corr_kernel(CorrArgs a) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[3 * kBufBytes];
     __shared__ uint32_t mwords[kMaskWindow];
-    __shared__ int s_flag;
 
     const int G = a.groups;
     const int64_t total = (int64_t)a.F * G * a.splits;
@@ -752,7 +762,7 @@ __global__ __launch_bounds__(kThreads, 1) void corr_kernel(CorrArgs a) {
     w /= G;
     const int split = (int)(w % a.splits);
     const int f = (int)(w / a.splits);
-    run_item<kAligned, kOverwrite>(a, f, gid, split, lds, mwords, &s_flag);
+    run_item<kAligned, kOverwrite>(a, f, gid, split, lds, mwords);
 }
 
 // ---------------------------------------------------------------------------
@@ -768,7 +778,6 @@ struct BatchInstance {
     int32_t N, F, T, B;
     int32_t nblk_mask, nb, groups, splits;
     int32_t steps_per_split, aligned;
-    int64_t counter_base;  // first arrival counter of this instance
     int64_t partial_base;  // first int32 of its partial tiles
 };
 
@@ -784,11 +793,10 @@ struct BatchItem {
 // (N % 4 == 0, 4-byte aligned frame); the host runs others on their own.
 __global__ __launch_bounds__(kThreads, 1) void batch_kernel(const BatchInstance *inst,
                                                             const BatchItem *items, int n_items,
-                                                            int *queue, int32_t *counters,
+                                                            int *queue,
                                                             int32_t *partials) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[3 * kBufBytes];
     __shared__ uint32_t mwords[kMaskWindow];
-    __shared__ int s_flag;
     __shared__ int s_item;
     for (;;) {
         __syncthreads();  // the previous item has released LDS
@@ -814,7 +822,6 @@ __global__ __launch_bounds__(kThreads, 1) void batch_kernel(const BatchInstance 
         a.vis = (int32_t *)ptr(bi.vis);
         a.count = (int64_t *)ptr(bi.count);
         a.partials = partials + u64(bi.partial_base);
-        a.counters = counters + u64(bi.counter_base);
         a.N = u32(bi.N);
         a.F = u32(bi.F);
         a.T = u32(bi.T);
@@ -824,7 +831,7 @@ __global__ __launch_bounds__(kThreads, 1) void batch_kernel(const BatchInstance 
         a.groups = u32(bi.groups);
         a.splits = u32(bi.splits);
         a.steps_per_split = u32(bi.steps_per_split);
-        run_item<true, false>(a, wf, wg, ws, lds, mwords, &s_flag);
+        run_item<true, false>(a, wf, wg, ws, lds, mwords);
     }
     if (threadIdx.x == 0) {
         int done = atomicAdd(&queue[1], 1);
@@ -833,6 +840,99 @@ __global__ __launch_bounds__(kThreads, 1) void batch_kernel(const BatchInstance 
             queue[1] = 0;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// merge of time chunks
+// ---------------------------------------------------------------------------
+
+// An instance whose time chunks are merged: chunk 0 has written its sums to
+// `vis`, chunks 1 .. splits-1 left their tiles in `partials`.
+struct MergeInst {
+    int32_t *vis;
+    int32_t *partials;
+    int N, nb, groups, splits;
+    int64_t block_begin;  // first merge block of the instance (batch lists)
+};
+
+// One wave adds chunks 1.. of its role's tiles of group `key` into vis;
+// the loads of three chunks are in flight together.
+template <int SHAPE>
+__device__ __forceinline__ void merge_tiles(const MergeInst &m, const Group &g, int64_t key,
+                                            int wave, int s0, int c0) {
+    using TL = Tiles<SHAPE>;
+    const int lane = threadIdx.x & 63;
+    const TileMap<SHAPE> map{g, s0, c0, m.N};
+    const int64_t f = key / m.groups;
+    const int64_t P = (int64_t)m.N * (m.N + 1) / 2;
+    int32_t *visf = m.vis + f * P * 2;
+#pragma unroll 1
+    for (int k = 0; k < TL::NT; ++k) {
+        v2i old[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int64_t idx = map.elem(k, v, lane);
+            old[v] = idx >= 0 ? *(const v2i *)(visf + 2 * idx) : (v2i){0, 0};
+        }
+        v16i re = (v16i){0}, im = (v16i){0};
+        for (int sp0 = 1; sp0 < m.splits; sp0 += 3) {
+            v4i ld[3][8];
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) {
+                const int sp = sp0 + jj < m.splits ? sp0 + jj : 1;
+                const int32_t *src = partial_tiles(m.partials, key, m.splits, sp, wave) +
+                                     (k * 8 * 64 + lane) * 4;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) ld[jj][v] = *(const v4i *)(src + v * 256);
+            }
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) {
+                if (sp0 + jj < m.splits) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            re[4 * v + c] += ld[jj][v][c];
+                            im[4 * v + c] += ld[jj][4 + v][c];
+                        }
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int64_t idx = map.elem(k, v, lane);
+            if (idx >= 0) *(v2i *)(visf + 2 * idx) = old[v] + (v2i){re[v], im[v]};
+        }
+    }
+}
+
+// merge block b of an instance = (group key, wave role) = (b / 8, b % 8)
+__device__ __forceinline__ void merge_block(const MergeInst &m, int64_t b) {
+    const int64_t key = b / kWaves;
+    const int wave = (int)(b % kWaves);
+    const Group g = make_group(m.nb, (int)(key % m.groups));
+    with_role(g, wave, [&](auto role, int s0, int c0) {
+        merge_tiles<decltype(role)::SHAPE>(m, g, key, wave, s0, c0);
+    });
+}
+
+// one instance: F * groups * 8 blocks of one wave
+__global__ __launch_bounds__(64) void merge_kernel(MergeInst m) { merge_block(m, blockIdx.x); }
+
+// a batch's chunked instances, sorted by block_begin; block b belongs to the
+// last instance whose first block is <= b
+__global__ __launch_bounds__(64) void merge_list_kernel(const MergeInst *list, int n) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (list[mid].block_begin <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const MergeInst m = list[lo];
+    merge_block(m, b - m.block_begin);
 }
 
 // ---------------------------------------------------------------------------

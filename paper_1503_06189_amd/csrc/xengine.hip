@@ -24,10 +24,15 @@ constexpr int kPlanSlots = 4;
 constexpr size_t kSlotBytes = (size_t)4 << 20;
 constexpr size_t kQueueBytes = 256;  // queue head and done counters, padded
 
+// sizes of a plan kept in a device slot
+struct SlotShape {
+    int n_inst = 0, n_items = 0, n_merges = 0;
+    int64_t merge_blocks = 0;
+};
+
 struct PlanSlot {
     bool used = false;
-    int n_items = 0;
-    int n_inst = 0;
+    SlotShape shape;
     std::vector<xe_instance> unaligned;  // instances run as plain launches
 };
 
@@ -102,15 +107,13 @@ xe_status check_frame(xe_handle h, const uint8_t *packed, int32_t N, int32_t F, 
     return XE_OK;
 }
 
-// Workspace layout: [counters: kCounterBytes][partial accumulators ...]
-constexpr size_t kCounterBytes = 1u << 20;
-// default workspace: time-chunk sums of a large batch (327 KB per chunked
-// tile group) with room to spare; small next to 288 GB of HBM
+// Workspace: the tiles of time chunks 1 .. splits-1 of every chunked tile
+// group (chunk 0 writes the output directly), 327,680 B per group and chunk.
+// The default leaves room for large batches and is small next to 288 GB.
 constexpr size_t kDefaultWorkspace = (size_t)1 << 30;
-constexpr int64_t kMaxKeys = kCounterBytes / sizeof(int32_t);
 
 size_t partial_bytes(int64_t keys, int splits) {
-    return splits > 1 ? (size_t)keys * splits * xe::kGroupPartial * sizeof(int32_t) : 0;
+    return splits > 1 ? (size_t)keys * (splits - 1) * xe::kGroupPartial * sizeof(int32_t) : 0;
 }
 
 // Returns false when time chunks are unavoidable but their partial sums do
@@ -131,7 +134,7 @@ bool fill_plan(int32_t N, int32_t F, int32_t T, int32_t n_cu, size_t ws_bytes,
         splits = xe::ceil_div(steps, sps);
     }
     // fewer chunks when their partial sums do not fit the workspace
-    while (splits > 1 && (keys > kMaxKeys || kCounterBytes + partial_bytes(keys, splits) > ws_bytes)) {
+    while (splits > 1 && partial_bytes(keys, splits) > ws_bytes) {
         int want = splits - 1;
         int next = xe::round_steps(xe::ceil_div(steps, want));
         if (next > max_sps) break;  // cannot merge chunks any further
@@ -144,8 +147,7 @@ bool fill_plan(int32_t N, int32_t F, int32_t T, int32_t n_cu, size_t ws_bytes,
     p->steps_per_split = sps;
     p->workgroups = keys * splits;
     p->mfma_tiles = xe::tiles_per_channel(nb);
-    return splits == 1 ||
-           (keys <= kMaxKeys && kCounterBytes + partial_bytes(keys, splits) <= ws_bytes);
+    return splits == 1 || partial_bytes(keys, splits) <= ws_bytes;
 }
 
 xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, int32_t N,
@@ -159,8 +161,7 @@ xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, i
     a.mask = mask;
     a.vis = vis;
     a.count = count;
-    a.counters = (int32_t *)h->workspace;
-    a.partials = (int32_t *)((char *)h->workspace + kCounterBytes);
+    a.partials = (int32_t *)h->workspace;
     a.N = N;
     a.F = F;
     a.T = T;
@@ -183,6 +184,22 @@ xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, i
         hipLaunchKernelGGL((xe::corr_kernel<false, false>), grid, block, 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "correlation launch");
+    if (p.splits > 1) {
+        // chunks 1.. into the output; stream order makes their tiles visible
+        xe::MergeInst m;
+        m.vis = vis;
+        m.partials = a.partials;
+        m.N = N;
+        m.nb = p.blocks;
+        m.groups = p.groups;
+        m.splits = p.splits;
+        m.block_begin = 0;
+        const int64_t blocks = (int64_t)F * p.groups * xe::kWaves;
+        if (blocks > 0x7fffffff) return fail(h, XE_ERR_ARG, "too many merge blocks");
+        hipLaunchKernelGGL(xe::merge_kernel, dim3((unsigned)blocks), dim3(64), 0, stream, m);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(h, e, "merge launch");
+    }
     return XE_OK;
 }
 
@@ -203,10 +220,17 @@ struct BatchPlan {
     std::vector<xe::BatchInstance> inst;
     std::vector<xe::BatchItem> items;
     std::vector<xe_instance> unaligned;
+    std::vector<xe::MergeInst> merges;  // chunked instances, for the merge pass
+    std::vector<int64_t> merge_base;    // their first partial value in the workspace
     int chunk_steps = 0;
-    int64_t counters = 0;    // arrival counters used
-    int64_t partials = 0;    // int32 partial values used
+    int64_t partials = 0;      // int32 partial values used
+    int64_t merge_blocks = 0;  // one-wave blocks of the merge pass
 };
+
+size_t plan_bytes(const BatchPlan &p) {
+    return kQueueBytes + p.inst.size() * sizeof(xe::BatchInstance) +
+           p.items.size() * sizeof(xe::BatchItem) + p.merges.size() * sizeof(xe::MergeInst);
+}
 
 // Work items of a batch: every (instance, channel, group, time chunk), with
 // time chunks of about `chunk_steps` 32-sample steps (0: enough items for
@@ -280,11 +304,20 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
         b.splits = splits;
         b.steps_per_split = sps;
         b.aligned = 1;
-        b.counter_base = plan->counters;
         b.partial_base = plan->partials;
         if (splits > 1) {
-            plan->counters += (int64_t)x.F * G;
-            plan->partials += (int64_t)x.F * G * splits * xe::kGroupPartial;
+            xe::MergeInst m;
+            m.vis = x.vis;
+            m.partials = nullptr;  // set from the workspace at launch
+            m.N = x.N;
+            m.nb = nb;
+            m.groups = G;
+            m.splits = splits;
+            m.block_begin = plan->merge_blocks;
+            plan->merges.push_back(m);
+            plan->merge_base.push_back(plan->partials);
+            plan->merge_blocks += (int64_t)x.F * G * xe::kWaves;
+            plan->partials += (int64_t)x.F * G * (splits - 1) * xe::kGroupPartial;
         }
         const int idx = (int)plan->inst.size();
         plan->inst.push_back(b);
@@ -299,41 +332,58 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
                      [](const Cost &a, const Cost &b) { return a.steps > b.steps; });
     plan->items.reserve(costs.size());
     for (const Cost &c : costs) plan->items.push_back(c.item);
-    if (plan->counters > kMaxKeys ||
-        kCounterBytes + (size_t)plan->partials * sizeof(int32_t) > ws_bytes)
+    if ((size_t)plan->partials * sizeof(int32_t) > ws_bytes)
         return fail(h, XE_ERR_WORKSPACE, "batch partial sums do not fit the workspace");
-    size_t bytes = kQueueBytes + plan->inst.size() * sizeof(xe::BatchInstance) +
-                   plan->items.size() * sizeof(xe::BatchItem);
-    if (bytes > kSlotBytes) return fail(h, XE_ERR_WORKSPACE, "batch work list too large");
+    if (plan->merge_blocks > 0x7fffffff) return fail(h, XE_ERR_ARG, "too many merge blocks");
+    if (plan_bytes(*plan) > kSlotBytes) return fail(h, XE_ERR_WORKSPACE, "batch work list too large");
     return XE_OK;
 }
 
-// Serialise a plan into slot layout: [queue][instances][items].
-void write_plan(const BatchPlan &p, char *dst) {
+// Slot layout: [queue][instances][items][merge list]; the merge list's
+// partial pointers are filled in from the handle's workspace.
+void write_plan(const BatchPlan &p, int32_t *workspace, char *dst) {
     memset(dst, 0, kQueueBytes);
     char *q = dst + kQueueBytes;
     memcpy(q, p.inst.data(), p.inst.size() * sizeof(xe::BatchInstance));
     q += p.inst.size() * sizeof(xe::BatchInstance);
     memcpy(q, p.items.data(), p.items.size() * sizeof(xe::BatchItem));
+    q += p.items.size() * sizeof(xe::BatchItem);
+    for (size_t k = 0; k < p.merges.size(); ++k) {
+        xe::MergeInst m = p.merges[k];
+        m.partials = workspace + p.merge_base[k];
+        memcpy(q, &m, sizeof m);
+        q += sizeof m;
+    }
 }
 
-size_t plan_bytes(const BatchPlan &p) {
-    return kQueueBytes + p.inst.size() * sizeof(xe::BatchInstance) +
-           p.items.size() * sizeof(xe::BatchItem);
+SlotShape shape_of(const BatchPlan &p) {
+    SlotShape sh;
+    sh.n_inst = (int)p.inst.size();
+    sh.n_items = (int)p.items.size();
+    sh.n_merges = (int)p.merges.size();
+    sh.merge_blocks = p.merge_blocks;
+    return sh;
 }
 
-xe_status launch_batch(xe_handle h, int slot, int n_inst, int n_items, hipStream_t stream) {
-    if (n_items == 0) return XE_OK;
+xe_status launch_batch(xe_handle h, int slot, const SlotShape &sh, hipStream_t stream) {
+    if (sh.n_items == 0) return XE_OK;
     char *base = (char *)h->plan_area + (size_t)slot * kSlotBytes;
     const xe::BatchInstance *bi = (const xe::BatchInstance *)(base + kQueueBytes);
     const xe::BatchItem *items = (const xe::BatchItem *)(base + kQueueBytes +
-                                                           n_inst * sizeof(xe::BatchInstance));
-    int grid = std::min(h->n_cu, n_items);
+                                                           sh.n_inst * sizeof(xe::BatchInstance));
+    const xe::MergeInst *merges =
+        (const xe::MergeInst *)((const char *)items + sh.n_items * sizeof(xe::BatchItem));
+    int grid = std::min(h->n_cu, sh.n_items);
     hipLaunchKernelGGL(xe::batch_kernel, dim3(grid), dim3(xe::kThreads), 0, stream, bi, items,
-                       n_items, (int *)base, (int32_t *)h->workspace,
-                       (int32_t *)((char *)h->workspace + kCounterBytes));
+                       sh.n_items, (int *)base, (int32_t *)h->workspace);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "batch launch");
+    if (sh.n_merges > 0) {
+        hipLaunchKernelGGL(xe::merge_list_kernel, dim3((unsigned)sh.merge_blocks), dim3(64), 0,
+                           stream, merges, sh.n_merges);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(h, e, "batch merge launch");
+    }
     return XE_OK;
 }
 
@@ -376,7 +426,6 @@ xe_status xe_create(xe_handle *out, int32_t hip_device, size_t workspace_bytes) 
     }
     h->n_cu = prop.multiProcessorCount;
     if (workspace_bytes == 0) workspace_bytes = kDefaultWorkspace;
-    if (workspace_bytes < kCounterBytes) workspace_bytes = kCounterBytes;
     {
         DeviceGuard g(hip_device);
         if (!g.ok) {
@@ -388,10 +437,8 @@ xe_status xe_create(xe_handle *out, int32_t hip_device, size_t workspace_bytes) 
             delete h;
             return XE_ERR_HIP;
         }
-        // arrival counters and batch queues start at zero; every launch
-        // leaves them at zero
-        e = hipMemset(h->workspace, 0, kCounterBytes);
-        if (e == hipSuccess) e = hipMalloc(&h->plan_area, (kRingSlots + kPlanSlots) * kSlotBytes);
+        // batch queues start at zero; every batch launch leaves them at zero
+        e = hipMalloc(&h->plan_area, (kRingSlots + kPlanSlots) * kSlotBytes);
         if (e == hipSuccess)
             e = hipMemset(h->plan_area, 0, (kRingSlots + kPlanSlots) * kSlotBytes);
         if (e == hipSuccess) e = hipHostMalloc(&h->staging, kRingSlots * kSlotBytes, 0);
@@ -518,11 +565,11 @@ xe_status xe_accumulate_batch(xe_handle h, const xe_instance *inst, int32_t n_in
         hipError_t e = hipEventSynchronize(h->ring_done[slot]);
         if (e != hipSuccess) return hip_fail(h, e, "batch ring wait");
         char *stage = (char *)h->staging + (size_t)slot * kSlotBytes;
-        write_plan(plan, stage);
+        write_plan(plan, (int32_t *)h->workspace, stage);
         e = hipMemcpyAsync((char *)h->plan_area + (size_t)slot * kSlotBytes, stage,
                            plan_bytes(plan), hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return hip_fail(h, e, "batch upload");
-        s = launch_batch(h, slot, (int)plan.inst.size(), (int)plan.items.size(), st);
+        s = launch_batch(h, slot, shape_of(plan), st);
         if (s != XE_OK) return s;
         e = hipEventRecord(h->ring_done[slot], st);
         if (e != hipSuccess) return hip_fail(h, e, "batch ring record");
@@ -553,15 +600,14 @@ xe_status xe_batch_plan(xe_handle h, const xe_instance *inst, int32_t n_inst,
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
     std::vector<char> host(plan_bytes(plan));
-    write_plan(plan, host.data());
+    write_plan(plan, (int32_t *)h->workspace, host.data());
     hipError_t e = hipMemcpy((char *)h->plan_area + (size_t)slot * kSlotBytes, host.data(),
                              host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(h, e, "plan upload");
     PlanSlot &ps = h->slots[slot];
     ps.used = true;
-    ps.n_items = (int)plan.items.size();
+    ps.shape = shape_of(plan);
     ps.unaligned = plan.unaligned;
-    ps.n_inst = (int)plan.inst.size();
     *plan_id = slot;
     return XE_OK;
 }
@@ -574,7 +620,7 @@ xe_status xe_batch_run(xe_handle h, int32_t plan_id, void *stream) {
     if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
     const PlanSlot &ps = h->slots[plan_id];
     hipStream_t st = (hipStream_t)stream;
-    xe_status s = launch_batch(h, plan_id, ps.n_inst, ps.n_items, st);
+    xe_status s = launch_batch(h, plan_id, ps.shape, st);
     if (s != XE_OK) return s;
     for (const xe_instance &x : ps.unaligned) {
         s = launch_corr(h, x.packed, x.loss_mask, x.N, x.F, x.T, x.B, x.vis, x.count, false, st);
