@@ -202,8 +202,9 @@ def serving_leg(torch, seconds: float):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # about 20 ms of warm-up: clocks settle before the timed region
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
@@ -310,7 +311,7 @@ def main():
     del packed, mask, vis, cnt, out
     torch.cuda.empty_cache()
     if not args.no_batched:
-        res["batched"] = batched_leg(torch, reps=max(3, args.steps // 2))
+        res["batched"] = batched_leg(torch, reps=max(3, min(20, args.steps)))
         torch.cuda.empty_cache()
     if not args.no_serving:
         res["serving"] = serving_leg(torch, args.serve_seconds)

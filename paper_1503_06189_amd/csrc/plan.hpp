@@ -1,24 +1,24 @@
 // plan.hpp -- how one frame is split into workgroups (host and device).
 //
 // The triangle of 32x32 input-block tiles (I <= J) of each channel is cut
-// into "super-blocks" of 8x8 tiles (256 x 256 inputs).  A workgroup of four
-// waves (one per SIMD, 256 accumulator registers each) takes one tile group:
+// into "super-blocks" of 8x8 tiles (256 x 256 inputs).  A workgroup of eight
+// waves (two per SIMD, 128 accumulator registers each) takes one tile group:
 //   * a diagonal super-block: a triangle of 36 tiles, 8 on the diagonal
 //     and 28 off it.  A diagonal tile costs half (one MFMA chain, 16
-//     accumulator registers).  Waves 0 and 1 take the 2 x 4 rectangles of
-//     tiles (0..1, 4..7) and (2..3, 4..7); waves 2 and 3 take the triangles
-//     of blocks 0..3 and 4..7 (4 diagonal + 6 off-diagonal tiles each);
+//     accumulator registers).  Waves 0..3 take the 1 x 4 rectangles of
+//     tiles (w, 4..7); waves 4..7 take the halves of the triangles of
+//     blocks 0..3 and 4..7 (2 diagonal tiles and 3 off-diagonal ones each);
 //   * half of an off-diagonal super-block: 4 tile rows x 8 tile columns.
-//     Wave w takes rows 2(w/2), 2(w/2)+1 and columns 4(w%2)..+3.
-// Every wave thus runs 32 MFMAs per staged step and reads 6 (rectangle)
-// or 8 (triangle) operand fragments per 16 MFMAs.  Super-blocks at the edge
-// of the triangle are padded: input blocks past ceil(N/32) are staged as
-// zeros and their tiles are computed but never stored, so every wave has a
-// fixed, compile-time tile pattern.  With ns = ceil(blocks / 8) super-rows
-// there are ns diagonal groups and ns(ns-1)/2 off-diagonal super-blocks of
-// two halves each: ns^2 groups.  Each workgroup integrates its tiles over
-// one chunk of the frame's time samples; chunks of the same tiles are added
-// into the output.
+//     Wave w takes row w % 4 and columns 4 (w / 4) .. + 3.
+// Every wave thus runs 16 MFMAs per staged step, and the two waves of a
+// SIMD (w and w + 4) together run 32.  Super-blocks at the edge of the
+// triangle are padded: input blocks past ceil(N/32) are staged as zeros and
+// their tiles are computed but never stored, so every wave has a fixed,
+// compile-time tile pattern.  With ns = ceil(blocks / 8) super-rows there
+// are ns diagonal groups and ns(ns-1)/2 off-diagonal super-blocks of two
+// halves each: ns^2 groups.  Each workgroup integrates its tiles over one
+// chunk of the frame's time samples; chunk 0 writes the output and a merge
+// kernel adds the other chunks.
 #pragma once
 
 #include <stdint.h>

@@ -14,7 +14,8 @@
 // A workgroup integrates one tile group (plan.hpp) of one channel over one
 // chunk of time.  Per staged step of 32 samples it
 //   1. loads the packed bytes of its input blocks with dword buffer loads
-//      along the input axis; the buffer range ends at the chunk;
+//      along the input axis (the buffer range ends at the chunk), kDepth
+//      steps ahead, into a ring of register sets;
 //   2. substitutes 0x88 (= 0) for lost samples, samples past the chunk and
 //      inputs past N, transposes 4x4 byte blocks in registers so that each
 //      dword holds 4 samples of one input, decodes nibbles to signed int8
@@ -24,16 +25,16 @@
 //      same K order, so the order of samples inside K does not change the
 //      sum;
 //   3. runs its tiles: A operand (rows) in Xr, Xp (and Xs) form, B Xr.
-// The loop is software-pipelined: the global loads for step s+2 and the
-// decode of step s+1 into the other LDS buffer overlap the MFMAs of step s;
-// one barrier per step; one wave per SIMD with 256 accumulator registers.
+// The loop is software-pipelined over three LDS buffers: the decode of step
+// s+2 and the operand reads of step s+1 overlap the MFMAs of step s; one
+// barrier per step; eight waves, two per SIMD, so that one wave's decode
+// and waits overlap the other's MFMAs.
 //
-// Output: a tile group owned by a single workgroup (one time chunk) is
-// written with plain stores (overwrite) or read-add-write (accumulate).
-// When time is split into chunks, every workgroup stores its int32 tiles in
-// the workspace; the last workgroup of a (channel, group) to arrive (device-
-// scope counter) adds all chunks and writes the result.  Integer sums, so
-// the order of chunks does not matter and the result is exact.
+// Output: chunk 0 of a tile group (or its only chunk) writes its tiles with
+// plain stores (overwrite) or read-add-write (accumulate).  Chunks 1.. store
+// their int32 tiles in the workspace, and merge_kernel, launched next on
+// the same stream, adds them into the output.  Integer sums, so the order of
+// chunks does not matter and the result is exact.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -855,19 +856,19 @@ struct MergeInst {
     int64_t block_begin;  // first merge block of the instance (batch lists)
 };
 
-// One wave adds chunks 1.. of its role's tiles of group `key` into vis;
-// the loads of three chunks are in flight together.
+// One wave adds chunks 1.. of tile k of its role in group `key` into vis;
+// the loads of three chunks and of the old sums are in flight together.
 template <int SHAPE>
-__device__ __forceinline__ void merge_tiles(const MergeInst &m, const Group &g, int64_t key,
-                                            int wave, int s0, int c0) {
+__device__ __forceinline__ void merge_tile(const MergeInst &m, const Group &g, int64_t key,
+                                           int wave, int k, int s0, int c0) {
     using TL = Tiles<SHAPE>;
+    if (k >= TL::NT) return;
     const int lane = threadIdx.x & 63;
     const TileMap<SHAPE> map{g, s0, c0, m.N};
     const int64_t f = key / m.groups;
     const int64_t P = (int64_t)m.N * (m.N + 1) / 2;
     int32_t *visf = m.vis + f * P * 2;
-#pragma unroll 1
-    for (int k = 0; k < TL::NT; ++k) {
+    {
         v2i old[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -906,17 +907,21 @@ __device__ __forceinline__ void merge_tiles(const MergeInst &m, const Group &g, 
     }
 }
 
-// merge block b of an instance = (group key, wave role) = (b / 8, b % 8)
+// merge block b of an instance = (group key, wave role, tile) =
+// (b / (8 kTilesPerWave), b / kTilesPerWave % 8, b % kTilesPerWave)
+constexpr int kMergeBlocksPerGroup = kWaves * kTilesPerWave;
+
 __device__ __forceinline__ void merge_block(const MergeInst &m, int64_t b) {
-    const int64_t key = b / kWaves;
-    const int wave = (int)(b % kWaves);
+    const int64_t key = b / kMergeBlocksPerGroup;
+    const int wave = (int)(b / kTilesPerWave % kWaves);
+    const int k = (int)(b % kTilesPerWave);
     const Group g = make_group(m.nb, (int)(key % m.groups));
     with_role(g, wave, [&](auto role, int s0, int c0) {
-        merge_tiles<decltype(role)::SHAPE>(m, g, key, wave, s0, c0);
+        merge_tile<decltype(role)::SHAPE>(m, g, key, wave, k, s0, c0);
     });
 }
 
-// one instance: F * groups * 8 blocks of one wave
+// one instance: F * groups * 8 * kTilesPerWave blocks of one wave
 __global__ __launch_bounds__(64) void merge_kernel(MergeInst m) { merge_block(m, blockIdx.x); }
 
 // a batch's chunked instances, sorted by block_begin; block b belongs to the

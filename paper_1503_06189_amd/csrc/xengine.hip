@@ -194,7 +194,7 @@ xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, i
         m.groups = p.groups;
         m.splits = p.splits;
         m.block_begin = 0;
-        const int64_t blocks = (int64_t)F * p.groups * xe::kWaves;
+        const int64_t blocks = (int64_t)F * p.groups * xe::kMergeBlocksPerGroup;
         if (blocks > 0x7fffffff) return fail(h, XE_ERR_ARG, "too many merge blocks");
         hipLaunchKernelGGL(xe::merge_kernel, dim3((unsigned)blocks), dim3(64), 0, stream, m);
         e = hipGetLastError();
@@ -316,7 +316,7 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
             m.block_begin = plan->merge_blocks;
             plan->merges.push_back(m);
             plan->merge_base.push_back(plan->partials);
-            plan->merge_blocks += (int64_t)x.F * G * xe::kWaves;
+            plan->merge_blocks += (int64_t)x.F * G * xe::kMergeBlocksPerGroup;
             plan->partials += (int64_t)x.F * G * (splits - 1) * xe::kGroupPartial;
         }
         const int idx = (int)plan->inst.size();

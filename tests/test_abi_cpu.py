@@ -164,27 +164,49 @@ def test_plan_query_shapes():
 
 
 def test_tile_groups_cover_the_triangle_once():
-    """Host model of the tile decomposition (four waves per group): every
-    (I <= J) block pair of the triangle is owned by exactly one tile of one
-    wave of one group, for many N, and every wave runs 32 MFMAs per step
-    (a diagonal tile is one chain, an off-diagonal tile two)."""
+    """Host model of the tile decomposition (eight waves per group, waves w
+    and w + 4 on one SIMD): every (I <= J) block pair of the triangle is
+    owned by exactly one tile of one wave of one group, for many N; every
+    wave runs 16 MFMAs per step (a diagonal tile is one chain, an
+    off-diagonal tile two) and holds at most 128 accumulator registers; the
+    staging work of a step is dealt evenly to the four SIMDs."""
+    def roles(diag):
+        out = []
+        for w in range(8):
+            if diag:
+                if w < 4:                       # row block w x columns 4..7
+                    q, pairs, upt = [], [(w, 4 + c) for c in range(4)], 1
+                elif w % 2 == 0:                # half A of triangle 0..3 / 4..7
+                    b = 2 * (w - 4)
+                    q, pairs, upt = [b, b + 1], [(b, b + c) for c in (1, 2, 3)], 1
+                else:                           # half B
+                    b = 2 * (w - 5)
+                    q = [b + 2, b + 3]
+                    pairs = [(b + 1, b + 2), (b + 1, b + 3), (b + 2, b + 3)]
+                    upt = 1
+            else:                               # row slot w % 4 x 4 column slots
+                c0 = 4 + 4 * (w // 4)
+                q, pairs, upt = [], [(w % 4, c0 + c) for c in range(4)], 2 if w < 4 else 1
+            out.append((q, pairs, upt))
+        return out
+
+    for diag in (True, False):
+        rs = roles(diag)
+        for q, pairs, upt in rs:
+            assert 2 * (len(q) + 2 * len(pairs)) == 16        # MFMAs per 32-sample step
+            assert 16 * len(q) + 32 * len(pairs) <= 128       # accumulator registers
+        units = [rs[w][2] + rs[w + 4][2] for w in range(4)]
+        assert len(set(units)) == 1                           # per-SIMD staging share
+        assert sum(r[2] for r in rs) * 64 == (8 if diag else 12) * 64  # units per step
+
     def groups(nb):
         ns = -(-nb // 8)
         out = []
         for gid in range(ns * ns):
             if gid < ns:
                 slots = [8 * gid + s for s in range(8)]
-                for w in range(4):
-                    if w < 2:      # rows 2w, 2w+1 x columns 4..7
-                        tiles = [(2 * w + r, 4 + c) for r in range(2) for c in range(4)]
-                        mfmas = 2 * 2 * len(tiles)
-                    else:          # triangle of blocks b..b+3
-                        b = 4 * (w - 2)
-                        q = [(b + k, b + k) for k in range(4)]
-                        o = [(b + r, b + c) for r in range(4) for c in range(r + 1, 4)]
-                        tiles = q + o
-                        mfmas = 2 * len(q) + 2 * 2 * len(o)
-                    assert mfmas == 32 and len(set(tiles)) == len(tiles)
+                for q, pairs, _ in roles(True):
+                    tiles = [(b, b) for b in q] + pairs
                     out += [(slots[r], slots[c]) for r, c in tiles]
             else:
                 q = gid - ns
@@ -195,11 +217,8 @@ def test_tile_groups_cover_the_triangle_once():
                     R += 1
                 C = R + 1 + p
                 slots = [8 * R + 4 * half + s for s in range(4)] + [8 * C + s for s in range(8)]
-                for w in range(4):
-                    c0 = 4 + 4 * (w % 2)
-                    tiles = [(2 * (w // 2) + r, c0 + c) for r in range(2) for c in range(4)]
-                    assert 2 * 2 * len(tiles) == 32
-                    out += [(slots[r], slots[c]) for r, c in tiles]
+                for _, pairs, _ in roles(False):
+                    out += [(slots[r], slots[c]) for r, c in pairs]
         return out
     for nb in (1, 2, 3, 7, 8, 9, 15, 16, 17, 33, 64, 128):
         allt = groups(nb)
