@@ -9,11 +9,12 @@ MFMA over the upper triangle, add, count) and the integration normalised
 region starts.
 
 Prints ONE JSON line.  Fields beyond the common ones:
-  roofline      the correlation kernel against the int8 MFMA peak: the
-                algorithmic ops per launch (8 per channel, upper-triangle
+  roofline      the correlation call (correlation kernel + the merge of
+                its time chunks) against the int8 MFMA peak: the
+                algorithmic ops per call (8 per channel, upper-triangle
                 pair and sample) over its average duration, timed with HIP
                 events on the stream it runs on; traffic = HBM bytes per
-                launch from the committed counter runs, when they were
+                call from the committed counter runs, when they were
                 taken on the current kernel source
   batched       128 uneven single-channel instances (N 64..1024, 1024 to
                 65536 samples) in one persistent launch replayed from a
@@ -297,6 +298,7 @@ def main():
                    "loss": "bernoulli 0.01 per 256-sample block",
                    "step": "accumulate one frame + normalize the integration"},
         "roofline": {
+            "kernel": "xe_accumulate call: corr_kernel + merge_kernel (chunks 1..3)",
             "bound": "mfma",
             "achieved": round(achieved_tops, 2),
             "peak": MFMA_INT8_PEAK_TOPS,
