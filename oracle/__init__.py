@@ -69,6 +69,17 @@ class Oracle:
                                                _p, _p, _p, _i64, _p]
         lib.oracle_normalize.restype = None
         lib.oracle_normalize.argtypes = [_p, _p, _i32, _i32, _p]
+        lib.oracle_flag_counters.restype = None
+        lib.oracle_flag_counters.argtypes = [_p, _p, _i32, _i32, _i32, _i32, _p, _p]
+        lib.oracle_flag_norm.restype = None
+        lib.oracle_flag_norm.argtypes = [_p, _p, _p, _i32, _i32, _p]
+        lib.oracle_apply_flags.restype = None
+        lib.oracle_apply_flags.argtypes = [_p, _p, _i32, _i32, _i32]
+        lib.oracle_correlate_flagged.restype = None
+        lib.oracle_correlate_flagged.argtypes = [_p, _p, _p, _i32, _i32, _i32, _i32,
+                                                 _p, _p]
+        lib.oracle_normalize_pairs.restype = None
+        lib.oracle_normalize_pairs.argtypes = [_p, _p, _i32, _i32, _p]
 
     # -- helpers ---------------------------------------------------------
     @staticmethod
@@ -82,6 +93,13 @@ class Oracle:
             if mask.shape != (F, (T + B - 1) // B):
                 raise ValueError("mask must be [F][ceil(T/B)]")
         return packed, mask, N, F, T
+
+    @staticmethod
+    def _flag_args(flags: np.ndarray, T: int, F: int, N: int) -> np.ndarray:
+        flags = np.ascontiguousarray(flags, dtype=np.uint32)
+        if flags.shape != (T, F, (N + 31) // 32):
+            raise ValueError("flags must be uint32 [T][F][ceil(N/32)]")
+        return flags
 
     # -- API ---------------------------------------------------------------
     def tri_index(self, N: int, i: int, j: int) -> int:
@@ -151,6 +169,68 @@ class Oracle:
             raise ValueError("vis must be [F][N(N+1)/2][2], count [F]")
         out = np.zeros((F, P, 2), dtype=np.float32)
         self._lib.oracle_normalize(_ptr(vis), _ptr(cnt), N, F, _ptr(out))
+        return out
+
+    # -- per-input flags (Sec. II-C) -----------------------------------------
+    def flag_counters(self, flags, mask, N: int, B: int = 256, c=None, d=None):
+        """Counters c [F][N] and intersections d [F][P] (diagonal = c) of
+        one frame's flags, added into ``c``/``d`` when given."""
+        flags = np.asarray(flags)
+        T, F = flags.shape[:2]
+        flags = self._flag_args(flags, T, F, N)
+        if mask is not None:
+            mask = np.ascontiguousarray(mask, dtype=np.uint8)
+            if mask.shape != (F, (T + B - 1) // B):
+                raise ValueError("mask must be [F][ceil(T/B)]")
+        P = N * (N + 1) // 2
+        c = np.zeros((F, N), dtype=np.int64) if c is None else c
+        d = np.zeros((F, P), dtype=np.int64) if d is None else d
+        if c.dtype != np.int64 or c.shape != (F, N) or not c.flags.c_contiguous:
+            raise ValueError("c must be contiguous int64 [F][N]")
+        if d.dtype != np.int64 or d.shape != (F, P) or not d.flags.c_contiguous:
+            raise ValueError("d must be contiguous int64 [F][P]")
+        self._lib.oracle_flag_counters(_ptr(flags), _ptr(mask), N, F, T, B,
+                                       _ptr(c), _ptr(d))
+        return c, d
+
+    def flag_norm(self, count, c, d) -> np.ndarray:
+        """Normalisation matrix n [F][P] = count_f - c_i - c_j + d_ij."""
+        count = np.ascontiguousarray(count, dtype=np.int64)
+        c = np.ascontiguousarray(c, dtype=np.int64)
+        d = np.ascontiguousarray(d, dtype=np.int64)
+        F, N = c.shape
+        if count.shape != (F,) or d.shape != (F, N * (N + 1) // 2):
+            raise ValueError("count [F], c [F][N], d [F][P] expected")
+        n = np.zeros_like(d)
+        self._lib.oracle_flag_norm(_ptr(count), _ptr(c), _ptr(d), N, F, _ptr(n))
+        return n
+
+    def apply_flags(self, packed, flags) -> np.ndarray:
+        """Copy of the frame with every flagged point set to 0 + 0i."""
+        out = np.array(packed, dtype=np.uint8, order="C", copy=True)
+        T, F, N = out.shape
+        flags = self._flag_args(flags, T, F, N)
+        self._lib.oracle_apply_flags(_ptr(out), _ptr(flags), N, F, T)
+        return out
+
+    def correlate_flagged(self, packed, mask, flags, B: int = 256):
+        packed, mask, N, F, T = self._frame_args(packed, mask, B)
+        flags = self._flag_args(flags, T, F, N)
+        vis = np.zeros((F, N * (N + 1) // 2, 2), dtype=np.int64)
+        cnt = np.zeros(F, dtype=np.int64)
+        self._lib.oracle_correlate_flagged(_ptr(packed), _ptr(mask), _ptr(flags),
+                                           N, F, T, B, _ptr(vis), _ptr(cnt))
+        return vis, cnt
+
+    def normalize_pairs(self, vis, n) -> np.ndarray:
+        vis = np.ascontiguousarray(vis, dtype=np.int64)
+        n = np.ascontiguousarray(n, dtype=np.int64)
+        F, P, two = vis.shape
+        N = int(round((np.sqrt(8 * P + 1) - 1) / 2))
+        if two != 2 or N * (N + 1) // 2 != P or n.shape != (F, P):
+            raise ValueError("vis must be [F][P][2], n [F][P]")
+        out = np.zeros((F, P, 2), dtype=np.float32)
+        self._lib.oracle_normalize_pairs(_ptr(vis), _ptr(n), N, F, _ptr(out))
         return out
 
 

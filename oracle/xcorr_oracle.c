@@ -28,12 +28,21 @@
  *             fraction of lost data is applied to the correlation matrix at
  *             the end of the integration (Sec. II-C).
  *
+ *   flags     per-input F-engine flags (Sec. II-C), bit-fields beside the
+ *             frame: flagged points are zeroed before correlation, and the
+ *             normalisation matrix counts, per baseline, the valid samples
+ *             where neither input is flagged.  The bookkeeping follows the
+ *             method's own steps (per-input counters, intersections per
+ *             sample, then count - c_i - c_j + d_ij); the flagged
+ *             correlation is the plain definition with both conditions.
+ *
  * Loop order follows the definition: channel, i, j >= i, then the sum over
  * t.  OpenMP may split the (f, i) loop across threads; every sum is exact,
  * so the thread count does not change any result.
  */
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 /* value of the high (real) nibble and of the low (imaginary) nibble */
 static int re_part(uint8_t byte) { return (int)(byte >> 4) - 8; }
@@ -77,14 +86,28 @@ void oracle_valid_counts(const uint8_t *mask, int32_t F, int32_t T, int32_t B,
     }
 }
 
-/* sum over valid t of x_i * conj(x_j) for one channel and one pair */
-static void pair_sum(const uint8_t *packed, const uint8_t *mask, int N, int F,
-                     int T, int B, int f, int i, int j, int64_t *re_out,
-                     int64_t *im_out)
+/* 1 when the per-input flag bit-fields (described below, Sec. II-C) mark
+ * input i of channel f at sample t */
+static int input_flagged(const uint32_t *flags, int N, int F, int f, int t,
+                         int i)
+{
+    int64_t W = ((int64_t)N + 31) / 32;
+    return (int)((flags[((int64_t)t * F + f) * W + i / 32] >> (i % 32)) & 1u);
+}
+
+/* sum over valid t of x_i * conj(x_j) for one channel and one pair; with
+ * per-input flags, samples where either input is flagged are skipped too */
+static void pair_sum_flagged(const uint8_t *packed, const uint8_t *mask,
+                             const uint32_t *flags, int N, int F, int T, int B,
+                             int f, int i, int j, int64_t *re_out,
+                             int64_t *im_out)
 {
     int64_t re = 0, im = 0;
     for (int t = 0; t < T; ++t) {
         if (!sample_valid(mask, F, T, B, f, t))
+            continue;
+        if (flags != NULL && (input_flagged(flags, N, F, f, t, i) ||
+                              input_flagged(flags, N, F, f, t, j)))
             continue;
         const uint8_t *row = packed + ((int64_t)t * F + f) * N;
         int ai = re_part(row[i]), bi = im_part(row[i]);
@@ -95,6 +118,13 @@ static void pair_sum(const uint8_t *packed, const uint8_t *mask, int N, int F,
     }
     *re_out = re;
     *im_out = im;
+}
+
+static void pair_sum(const uint8_t *packed, const uint8_t *mask, int N, int F,
+                     int T, int B, int f, int i, int j, int64_t *re_out,
+                     int64_t *im_out)
+{
+    pair_sum_flagged(packed, mask, NULL, N, F, T, B, f, i, j, re_out, im_out);
 }
 
 /* V over one frame, overwriting vis [F][P][2] and count [F] */
@@ -177,4 +207,122 @@ void oracle_normalize(const int64_t *vis, const int64_t *count, int32_t N,
             out[k] = n == 0 ? 0.0f : (float)((double)vis[k] / (double)n);
         }
     }
+}
+
+/* ---------------------------------------------------------------------
+ * Per-input flags (Sec. II-C).  Besides whole lost packets, the F-engine
+ * flags single data points (range or sampling faults); those points are
+ * zeroed before the correlator sees them, so baseline (i, j) integrates
+ * fewer samples than its channel's valid count.  The flags arrive as
+ * bit-fields: flags[t][f][w] is a 32-bit word, W = ceil(N/32) words per
+ * (sample, channel), bit i%32 of word i/32 set when input i is flagged.
+ * Bits past input N-1 in the last word carry nothing.  A lost sample
+ * (packet mask) brings no footer, so its flags are never counted: the
+ * loss counter already removes that sample from every baseline.
+ * --------------------------------------------------------------------- */
+
+/* Flag bookkeeping as the method describes it, added into c and d:
+ *   c[f][i]           number of valid samples where input i is flagged
+ *                     (the per-input, per-frequency counters);
+ *   d[f][tri(i, j)]   for i < j, number of valid samples where i and j are
+ *                     flagged together (the intersections recorded per
+ *                     sample); on the diagonal d[f][tri(i, i)] = c[f][i],
+ *                     an input meeting itself in every flagged sample.
+ * Each sample's bit-field is read a 32-bit word at a time and bits are
+ * extracted only from non-zero words; the flagged inputs of the sample are
+ * listed and every pair of the list is counted, O(E^2) for E flags. */
+void oracle_flag_counters(const uint32_t *flags, const uint8_t *mask,
+                          int32_t N, int32_t F, int32_t T, int32_t B,
+                          int64_t *c, int64_t *d)
+{
+    int64_t W = ((int64_t)N + 31) / 32;
+    int64_t P = oracle_num_pairs(N);
+    int *listed = (int *)malloc(((size_t)N + 1) * sizeof(int));
+    if (listed == NULL)
+        return;
+    for (int f = 0; f < F; ++f) {
+        for (int t = 0; t < T; ++t) {
+            if (!sample_valid(mask, F, T, B, f, t))
+                continue;
+            const uint32_t *field = flags + ((int64_t)t * F + f) * W;
+            int E = 0;
+            for (int64_t w = 0; w < W; ++w) {
+                uint32_t word = field[w];
+                if (word == 0)
+                    continue;
+                for (int b = 0; b < 32 && w * 32 + b < N; ++b)
+                    if ((word >> b) & 1u)
+                        listed[E++] = (int)(w * 32 + b);
+            }
+            for (int k = 0; k < E; ++k) {
+                int i = listed[k];
+                c[(int64_t)f * N + i] += 1;
+                d[(int64_t)f * P + oracle_tri_index(N, i, i)] += 1;
+                for (int l = k + 1; l < E; ++l)
+                    d[(int64_t)f * P + oracle_tri_index(N, i, listed[l])] += 1;
+            }
+        }
+    }
+    free(listed);
+}
+
+/* Normalisation matrix, overwriting n [F][P]: the channel's valid-sample
+ * count (frame samples less the packet-loss counter) less the flag
+ * counters of both inputs, plus their intersection, which was subtracted
+ * twice:  n_ij = count_f - c_i - c_j + d_ij, and n_ii = count_f - c_i. */
+void oracle_flag_norm(const int64_t *count, const int64_t *c, const int64_t *d,
+                      int32_t N, int32_t F, int64_t *n)
+{
+    int64_t P = oracle_num_pairs(N);
+    for (int f = 0; f < F; ++f)
+        for (int i = 0; i < N; ++i)
+            for (int j = i; j < N; ++j) {
+                int64_t p = (int64_t)f * P + oracle_tri_index(N, i, j);
+                n[p] = count[f] - c[(int64_t)f * N + i] - c[(int64_t)f * N + j] + d[p];
+            }
+}
+
+/* Zero every flagged data point of a frame in place: byte 0x88 decodes to
+ * 0 + 0i.  This is what happens to flagged points before correlation. */
+void oracle_apply_flags(uint8_t *packed, const uint32_t *flags, int32_t N,
+                        int32_t F, int32_t T)
+{
+    for (int t = 0; t < T; ++t)
+        for (int f = 0; f < F; ++f)
+            for (int i = 0; i < N; ++i)
+                if (input_flagged(flags, N, F, f, t, i))
+                    packed[((int64_t)t * F + f) * N + i] = 0x88;
+}
+
+/* V of a frame with per-input flags, overwriting vis [F][P][2] and count
+ * [F]: the sum over samples that are valid and where neither input is
+ * flagged; count is the channel's valid-sample count, as without flags. */
+void oracle_correlate_flagged(const uint8_t *packed, const uint8_t *mask,
+                              const uint32_t *flags, int32_t N, int32_t F,
+                              int32_t T, int32_t B, int64_t *vis,
+                              int64_t *count)
+{
+    int64_t P = oracle_num_pairs(N);
+#pragma omp parallel for collapse(2) schedule(dynamic)
+    for (int f = 0; f < F; ++f)
+        for (int i = 0; i < N; ++i)
+            for (int j = i; j < N; ++j) {
+                int64_t *out = vis + ((int64_t)f * P + oracle_tri_index(N, i, j)) * 2;
+                pair_sum_flagged(packed, mask, flags, N, F, T, B, f, i, j,
+                                 &out[0], &out[1]);
+            }
+    oracle_valid_counts(mask, F, T, B, count);
+}
+
+/* out [F][P][2] = V / n_ij per baseline, in double rounded once to float;
+ * 0 where n_ij == 0 */
+void oracle_normalize_pairs(const int64_t *vis, const int64_t *n, int32_t N,
+                            int32_t F, float *out)
+{
+    int64_t P = oracle_num_pairs(N);
+    for (int64_t q = 0; q < (int64_t)F * P; ++q)
+        for (int k = 0; k < 2; ++k) {
+            int64_t m = n[q];
+            out[2 * q + k] = m == 0 ? 0.0f : (float)((double)vis[2 * q + k] / (double)m);
+        }
 }

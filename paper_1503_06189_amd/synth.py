@@ -17,6 +17,9 @@ time samples and is used by the GPU unmodified):
   of ``B`` samples, non-zero = the block was lost.  The last block may be
   partial.  Lost samples are written as ``0x88`` (value zero, the paper's
   zero fill, Sec. II-A.2) unless a test asks for garbage bytes there.
+* ``flags``   ``uint32[T][F][ceil(N/32)]`` -- per-input F-engine flags as
+  bit-fields, bit ``i % 32`` of word ``i // 32`` set when input ``i`` is
+  flagged at that sample and channel (Sec. II-C).
 
 Workload recipes (sizes from Sec. I, Sec. II-A, Sec. III and Table I: N=256
 inputs, 64 channels per server, 32-256 MB frames, N=16 and N=2048 scaling
@@ -141,6 +144,77 @@ def fill_lost(packed: np.ndarray, mask: Optional[np.ndarray], B: int,
             packed[t0:t1, f, :] = rng.integers(0, 256, (t1 - t0, N), dtype=np.uint8)
         else:
             raise ValueError(fill)
+
+
+# ---------------------------------------------------------------------------
+# per-input flags (F-engine range / sampling faults, Sec. II-C)
+# ---------------------------------------------------------------------------
+
+def flag_words(N: int) -> int:
+    """32-bit words per (sample, channel) bit-field."""
+    return (N + 31) // 32
+
+
+def pack_flags(bits: np.ndarray) -> np.ndarray:
+    """bool [T][F][N] -> uint32 [T][F][ceil(N/32)]; bit i%32 of word i/32."""
+    bits = np.asarray(bits, dtype=bool)
+    T, F, N = bits.shape
+    W = flag_words(N)
+    padded = np.zeros((T, F, W * 32), dtype=np.uint8)
+    padded[:, :, :N] = bits
+    by = np.packbits(padded.reshape(T, F, W, 4, 8), axis=-1, bitorder="little")
+    return np.ascontiguousarray(by.reshape(T, F, W, 4)).view("<u4").reshape(T, F, W)
+
+
+def unpack_flags(words: np.ndarray, N: int) -> np.ndarray:
+    """uint32 [T][F][W] bit-fields -> bool [T][F][N] (padding bits dropped)."""
+    words = np.ascontiguousarray(words, dtype="<u4")
+    T, F, W = words.shape
+    by = words.view(np.uint8).reshape(T, F, W * 4)
+    bits = np.unpackbits(by, axis=-1, bitorder="little")
+    return bits[:, :, :N].astype(bool)
+
+
+def fengine_flags(rng: np.random.Generator, T: int, F: int, N: int,
+                  rate: float, mean_run: float = 32.0,
+                  garbage_padding: bool = False) -> np.ndarray:
+    """Bursty per-input flags as uint32 bit-fields [T][F][ceil(N/32)].
+
+    Each (channel, input) sees flag runs (a saturating ADC, a range fault)
+    that start as a Poisson process in time with ``rate / mean_run`` starts
+    per sample and last a geometric number of samples of mean
+    ``mean_run``, so about ``rate`` of all points are flagged.  With
+    ``garbage_padding`` the bits past input N-1 of the last word are
+    random, which a consumer must ignore.  Draw order: run counts, starts,
+    lengths, padding.
+    """
+    bits = np.zeros((T, F, N), dtype=bool)
+    if rate > 0 and T > 0:
+        lam = rate * T / mean_run
+        runs = rng.poisson(lam, (F, N))
+        total = int(runs.sum())
+        fi = np.repeat(np.arange(F * N), runs.ravel())
+        start = rng.integers(0, T, total)
+        length = rng.geometric(1.0 / mean_run, total)
+        for k in range(total):
+            f, i = divmod(int(fi[k]), N)
+            bits[start[k]:start[k] + length[k], f, i] = True
+    words = pack_flags(bits)
+    if garbage_padding and N % 32:
+        pad = ~np.uint32((1 << (N % 32)) - 1)
+        junk = rng.integers(0, 2 ** 32, (T, F), dtype=np.uint32) & pad
+        words[:, :, -1] |= junk
+    return words
+
+
+def random_flags(rng: np.random.Generator, T: int, F: int, N: int,
+                 p: float, garbage_padding: bool = True) -> np.ndarray:
+    """Independent flags with probability p per point (dense stress case)."""
+    words = pack_flags(rng.random((T, F, N)) < p)
+    if garbage_padding and N % 32:
+        pad = ~np.uint32((1 << (N % 32)) - 1)
+        words[:, :, -1] |= rng.integers(0, 2 ** 32, (T, F), dtype=np.uint32) & pad
+    return words
 
 
 # ---------------------------------------------------------------------------

@@ -317,6 +317,131 @@ def pin_normalize_rounding(orc):
                     (f, p, c, float(exact), float(got))
 
 
+# ---------------------------------------------------------------------------
+# per-input flags (Sec. II-C)
+# ---------------------------------------------------------------------------
+
+def _flag_case(seed, N=37, F=3, T=70, B=8, p=0.25, p_loss=0.2):
+    """Random values, a loss mask and dense random flags with garbage in the
+    padding bits, one all-ones bit-field and one column of zero words."""
+    rng = np.random.default_rng(seed)
+    re, im = _values(rng, (T, F, N))
+    packed = _frame_from_values(re, im)
+    mask = synth.bernoulli_mask(rng, F, T, B, p_loss)
+    flags = synth.random_flags(rng, T, F, N, p, garbage_padding=True)
+    flags[3, 1, :] = 0xFFFFFFFF
+    flags[5, :, 0] = 0
+    return re, im, packed, mask, flags, B
+
+
+def pin_flag_counts_brute_force(orc):
+    """Counters, intersections and the normalisation matrix against direct
+    counting on unpacked bits: c_i = #valid samples with i flagged, d_ij =
+    #valid samples with both flagged, n_ij = #valid samples with neither
+    flagged (a 0/1 matrix product); counters add up across frames."""
+    for seed, N, T in ((31, 37, 70), (32, 64, 64), (33, 5, 33)):
+        re, im, packed, mask, flags, B = _flag_case(seed, N=N, T=T)
+        F = packed.shape[1]
+        valid = _expand_mask(mask, T, B)                       # [T][F]
+        fl = synth.unpack_flags(flags, N) & valid[:, :, None]
+        ok = valid[:, :, None] & ~synth.unpack_flags(flags, N)
+        c, d = orc.flag_counters(flags, mask, N, B)
+        cnt = orc.valid_counts(mask, F, T, B)
+        n = orc.flag_norm(cnt, c, d)
+        iu, ju = np.triu_indices(N)
+        for f in range(F):
+            A = fl[:, f, :].astype(np.int64)
+            O = ok[:, f, :].astype(np.int64)
+            D = A.T @ A
+            G = O.T @ O
+            assert (c[f] == A.sum(0)).all(), (seed, f)
+            assert (d[f] == D[iu, ju]).all(), (seed, f)
+            assert (n[f] == G[iu, ju]).all(), (seed, f)
+        # two halves of a frame (split on a block edge) add up to the whole
+        h = (T // 2) // B * B
+        if 0 < h < T:
+            c2, d2 = orc.flag_counters(flags[:h], mask[:, :h // B], N, B)
+            orc.flag_counters(flags[h:], mask[:, h // B:], N, B, c2, d2)
+            assert (c2 == c).all() and (d2 == d).all(), seed
+
+
+def pin_flagged_correlation(orc):
+    """Flagged points contribute nothing: V with flags equals numpy's
+    complex product of the values with flagged and lost points set to 0,
+    and equals the plain correlation of the frame whose flagged points
+    were zeroed (0x88); zeroing touches flagged points only."""
+    re, im, packed, mask, flags, B = _flag_case(34, N=37, T=70)
+    T, F, N = packed.shape
+    bits = synth.unpack_flags(flags, N)
+    valid = _expand_mask(mask, T, B)
+    vis, cnt = orc.correlate_flagged(packed, mask, flags, B)
+    x = (re + 1j * im) * (valid[:, :, None] & ~bits)
+    iu, ju = np.triu_indices(N)
+    for f in range(F):
+        X = x[:, f, :]
+        V = X.T @ X.conj()
+        assert (vis[f, :, 0] == np.rint(V[iu, ju].real)).all(), f
+        assert (vis[f, :, 1] == np.rint(V[iu, ju].imag)).all(), f
+    assert (cnt == orc.valid_counts(mask, F, T, B)).all()
+    z = orc.apply_flags(packed, flags)
+    assert (z[bits] == synth.ZERO_BYTE).all()
+    assert (z[~bits] == packed[~bits]).all()
+    vis2, cnt2 = orc.correlate(z, mask, B)
+    assert (vis2 == vis).all() and (cnt2 == cnt).all()
+
+
+def pin_flag_normalize(orc):
+    """Input i held at a constant x_i: every baseline with n_ij > 0
+    normalises to exactly x_i conj(x_j), an input flagged at every sample
+    has n = 0 on its row and column and normalises to 0, and without flags
+    n_ij is the channel's valid count.  Random V/n rounds to within half an
+    ulp of the exact rational."""
+    rng = np.random.default_rng(35)
+    N, F, T, B = 40, 2, 96, 16
+    xr = rng.integers(-7, 8, N)
+    xi = rng.integers(-7, 8, N)
+    packed = _frame_from_values(np.broadcast_to(xr, (T, F, N)),
+                                np.broadcast_to(xi, (T, F, N)))
+    mask = synth.bernoulli_mask(rng, F, T, B, 0.25)
+    bits = rng.random((T, F, N)) < 0.3
+    bits[:, 1, 7] = True
+    flags = synth.pack_flags(bits)
+    vis, cnt = orc.correlate_flagged(packed, mask, flags, B)
+    c, d = orc.flag_counters(flags, mask, N, B)
+    n = orc.flag_norm(cnt, c, d)
+    out = orc.normalize_pairs(vis, n)
+    iu, ju = np.triu_indices(N)
+    want_re = xr[iu] * xr[ju] + xi[iu] * xi[ju]
+    want_im = xi[iu] * xr[ju] - xr[iu] * xi[ju]
+    for f in range(F):
+        pos = n[f] > 0
+        assert (out[f, pos, 0] == want_re[pos]).all(), f
+        assert (out[f, pos, 1] == want_im[pos]).all(), f
+        assert not out[f, ~pos].any(), f
+        assert (n[f] < cnt[f]).any() and pos.any(), f
+    row7 = (iu == 7) | (ju == 7)
+    assert not n[1, row7].any()
+    c0, d0 = orc.flag_counters(np.zeros_like(flags), mask, N, B)
+    assert (orc.flag_norm(cnt, c0, d0) == cnt[:, None]).all()
+    # rounding of V / n_ij for arbitrary values
+    P = N * (N + 1) // 2
+    rv = rng.integers(-2 ** 31 + 1, 2 ** 31 - 1, (F, P, 2)).astype(np.int64)
+    rn = rng.integers(0, 2 ** 24, (F, P)).astype(np.int64)
+    rn[0, :5] = 0
+    ro = orc.normalize_pairs(rv, rn)
+    for f in range(F):
+        for p in range(0, P, 7):
+            for k in range(2):
+                if rn[f, p] == 0:
+                    assert ro[f, p, k] == 0
+                    continue
+                exact = Fraction(int(rv[f, p, k]), int(rn[f, p]))
+                got = Fraction(float(ro[f, p, k]))
+                m, e = np.frexp(np.float32(float(exact)))
+                half_ulp = Fraction(2) ** (int(e) - 25)
+                assert abs(got - exact) <= half_ulp * (1 + Fraction(1, 2 ** 28)), (f, p, k)
+
+
 PINS = [
     pin_decode_roundtrip,
     pin_tri_index,
@@ -331,4 +456,7 @@ PINS = [
     pin_overflow_edge,
     pin_pairs_subset,
     pin_normalize_rounding,
+    pin_flag_counts_brute_force,
+    pin_flagged_correlation,
+    pin_flag_normalize,
 ]

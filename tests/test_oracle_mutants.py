@@ -24,7 +24,7 @@ MUTANTS = [
     ("offset_7", "return (int)(byte & 15) - 8; }", "return (int)(byte & 15) - 7; }", 1),
     ("mask_block_index", "+ t / B]", "+ (t + 1) / B % nblk]", 1),
     ("mask_transposed", "mask[(int64_t)f * nblk + t / B]", "mask[(int64_t)(t / B) * F + f]", 1),
-    ("loss_ignored", "            continue;\n", "            ;\n", 1),
+    ("loss_ignored", "            continue;\n        if (flags != NULL", "            ;\n        if (flags != NULL", 1),
     ("count_ignores_loss", "            n += sample_valid(mask, F, T, B, f, t);\n        count[f] = n;",
      "            n += 1;\n        count[f] = n;", 1),
     ("transposed_operand",
@@ -37,6 +37,24 @@ MUTANTS = [
     ("normalize_zero_count", "n == 0 ? 0.0f : ", "", 1),
     ("tri_index_column_major", "return i * N - i * (i - 1) / 2 + (j - i);",
      "return j * (j + 1) / 2 + i;", 1),
+    # per-input flags (Sec. II-C)
+    ("flag_no_intersection",
+     "d[(int64_t)f * P + oracle_tri_index(N, i, listed[l])] += 1;", "(void)l;", 1),
+    ("flag_diagonal_missing",
+     "d[(int64_t)f * P + oracle_tri_index(N, i, i)] += 1;", ";", 1),
+    ("flag_counts_lost_samples",
+     "continue;\n            const uint32_t *field", ";\n            const uint32_t *field", 1),
+    ("flag_bit_order", "if ((word >> b) & 1u)", "if ((word >> (31 - b)) & 1u)", 1),
+    ("flag_fast_path_inverted", "if (word == 0)\n                    continue;",
+     "if (word != 0)\n                    continue;", 1),
+    ("flag_norm_intersection_sign", "+ d[p];", "- d[p];", 1),
+    ("flag_norm_one_counter", " - c[(int64_t)f * N + j] + d[p];", " + d[p];", 1),
+    ("flag_zero_byte", "= 0x88;", "= 0x00;", 1),
+    ("flagged_one_side", "(input_flagged(flags, N, F, f, t, i) ||\n", "(0 ||\n", 1),
+    ("flag_word_bit", "i / 32] >> (i % 32))", "i / 32] >> (31 - i % 32))", 1),
+    ("normalize_pairs_float",
+     "(float)((double)vis[2 * q + k] / (double)m)", "(float)vis[2 * q + k] / (float)m", 1),
+    ("normalize_pairs_zero", "m == 0 ? 0.0f : ", "", 1),
 ]
 
 
