@@ -97,8 +97,8 @@ class Oracle:
     @staticmethod
     def _flag_args(flags: np.ndarray, T: int, F: int, N: int) -> np.ndarray:
         flags = np.ascontiguousarray(flags, dtype=np.uint32)
-        if flags.shape != (T, F, (N + 31) // 32):
-            raise ValueError("flags must be uint32 [T][F][ceil(N/32)]")
+        if flags.shape != (F, T, (N + 31) // 32):
+            raise ValueError("flags must be uint32 [F][T][ceil(N/32)]")
         return flags
 
     # -- API ---------------------------------------------------------------
@@ -176,7 +176,7 @@ class Oracle:
         """Counters c [F][N] and intersections d [F][P] (diagonal = c) of
         one frame's flags, added into ``c``/``d`` when given."""
         flags = np.asarray(flags)
-        T, F = flags.shape[:2]
+        F, T = flags.shape[:2]
         flags = self._flag_args(flags, T, F, N)
         if mask is not None:
             mask = np.ascontiguousarray(mask, dtype=np.uint8)

@@ -88,11 +88,11 @@ void oracle_valid_counts(const uint8_t *mask, int32_t F, int32_t T, int32_t B,
 
 /* 1 when the per-input flag bit-fields (described below, Sec. II-C) mark
  * input i of channel f at sample t */
-static int input_flagged(const uint32_t *flags, int N, int F, int f, int t,
+static int input_flagged(const uint32_t *flags, int N, int T, int f, int t,
                          int i)
 {
     int64_t W = ((int64_t)N + 31) / 32;
-    return (int)((flags[((int64_t)t * F + f) * W + i / 32] >> (i % 32)) & 1u);
+    return (int)((flags[((int64_t)f * T + t) * W + i / 32] >> (i % 32)) & 1u);
 }
 
 /* sum over valid t of x_i * conj(x_j) for one channel and one pair; with
@@ -106,8 +106,8 @@ static void pair_sum_flagged(const uint8_t *packed, const uint8_t *mask,
     for (int t = 0; t < T; ++t) {
         if (!sample_valid(mask, F, T, B, f, t))
             continue;
-        if (flags != NULL && (input_flagged(flags, N, F, f, t, i) ||
-                              input_flagged(flags, N, F, f, t, j)))
+        if (flags != NULL && (input_flagged(flags, N, T, f, t, i) ||
+                              input_flagged(flags, N, T, f, t, j)))
             continue;
         const uint8_t *row = packed + ((int64_t)t * F + f) * N;
         int ai = re_part(row[i]), bi = im_part(row[i]);
@@ -214,8 +214,8 @@ void oracle_normalize(const int64_t *vis, const int64_t *count, int32_t N,
  * flags single data points (range or sampling faults); those points are
  * zeroed before the correlator sees them, so baseline (i, j) integrates
  * fewer samples than its channel's valid count.  The flags arrive as
- * bit-fields: flags[t][f][w] is a 32-bit word, W = ceil(N/32) words per
- * (sample, channel), bit i%32 of word i/32 set when input i is flagged.
+ * bit-fields: flags[f][t][w] is a 32-bit word, W = ceil(N/32) words per
+ * (channel, sample), bit i%32 of word i/32 set when input i is flagged.
  * Bits past input N-1 in the last word carry nothing.  A lost sample
  * (packet mask) brings no footer, so its flags are never counted: the
  * loss counter already removes that sample from every baseline.
@@ -244,7 +244,7 @@ void oracle_flag_counters(const uint32_t *flags, const uint8_t *mask,
         for (int t = 0; t < T; ++t) {
             if (!sample_valid(mask, F, T, B, f, t))
                 continue;
-            const uint32_t *field = flags + ((int64_t)t * F + f) * W;
+            const uint32_t *field = flags + ((int64_t)f * T + t) * W;
             int E = 0;
             for (int64_t w = 0; w < W; ++w) {
                 uint32_t word = field[w];
@@ -290,7 +290,7 @@ void oracle_apply_flags(uint8_t *packed, const uint32_t *flags, int32_t N,
     for (int t = 0; t < T; ++t)
         for (int f = 0; f < F; ++f)
             for (int i = 0; i < N; ++i)
-                if (input_flagged(flags, N, F, f, t, i))
+                if (input_flagged(flags, N, T, f, t, i))
                     packed[((int64_t)t * F + f) * N + i] = 0x88;
 }
 

@@ -17,9 +17,9 @@ time samples and is used by the GPU unmodified):
   of ``B`` samples, non-zero = the block was lost.  The last block may be
   partial.  Lost samples are written as ``0x88`` (value zero, the paper's
   zero fill, Sec. II-A.2) unless a test asks for garbage bytes there.
-* ``flags``   ``uint32[T][F][ceil(N/32)]`` -- per-input F-engine flags as
-  bit-fields, bit ``i % 32`` of word ``i // 32`` set when input ``i`` is
-  flagged at that sample and channel (Sec. II-C).
+* ``flags``   ``uint32[F][T][ceil(N/32)]`` -- per-input F-engine flags as
+  bit-fields, channel-major, bit ``i % 32`` of word ``i // 32`` set when
+  input ``i`` is flagged at that channel and sample (Sec. II-C).
 
 Workload recipes (sizes from Sec. I, Sec. II-A, Sec. III and Table I: N=256
 inputs, 64 channels per server, 32-256 MB frames, N=16 and N=2048 scaling
@@ -156,29 +156,31 @@ def flag_words(N: int) -> int:
 
 
 def pack_flags(bits: np.ndarray) -> np.ndarray:
-    """bool [T][F][N] -> uint32 [T][F][ceil(N/32)]; bit i%32 of word i/32."""
-    bits = np.asarray(bits, dtype=bool)
-    T, F, N = bits.shape
+    """bool [T][F][N] (frame order) -> uint32 [F][T][ceil(N/32)] bit-fields;
+    bit i%32 of word i/32."""
+    bits = np.asarray(bits, dtype=bool).transpose(1, 0, 2)
+    F, T, N = bits.shape
     W = flag_words(N)
-    padded = np.zeros((T, F, W * 32), dtype=np.uint8)
+    padded = np.zeros((F, T, W * 32), dtype=np.uint8)
     padded[:, :, :N] = bits
-    by = np.packbits(padded.reshape(T, F, W, 4, 8), axis=-1, bitorder="little")
-    return np.ascontiguousarray(by.reshape(T, F, W, 4)).view("<u4").reshape(T, F, W)
+    by = np.packbits(padded.reshape(F, T, W, 4, 8), axis=-1, bitorder="little")
+    return np.ascontiguousarray(by.reshape(F, T, W, 4)).view("<u4").reshape(F, T, W)
 
 
 def unpack_flags(words: np.ndarray, N: int) -> np.ndarray:
-    """uint32 [T][F][W] bit-fields -> bool [T][F][N] (padding bits dropped)."""
+    """uint32 [F][T][W] bit-fields -> bool [T][F][N] in frame order
+    (padding bits dropped)."""
     words = np.ascontiguousarray(words, dtype="<u4")
-    T, F, W = words.shape
-    by = words.view(np.uint8).reshape(T, F, W * 4)
+    F, T, W = words.shape
+    by = words.view(np.uint8).reshape(F, T, W * 4)
     bits = np.unpackbits(by, axis=-1, bitorder="little")
-    return bits[:, :, :N].astype(bool)
+    return bits[:, :, :N].astype(bool).transpose(1, 0, 2)
 
 
 def fengine_flags(rng: np.random.Generator, T: int, F: int, N: int,
                   rate: float, mean_run: float = 32.0,
                   garbage_padding: bool = False) -> np.ndarray:
-    """Bursty per-input flags as uint32 bit-fields [T][F][ceil(N/32)].
+    """Bursty per-input flags as uint32 bit-fields [F][T][ceil(N/32)].
 
     Each (channel, input) sees flag runs (a saturating ADC, a range fault)
     that start as a Poisson process in time with ``rate / mean_run`` starts
@@ -202,7 +204,7 @@ def fengine_flags(rng: np.random.Generator, T: int, F: int, N: int,
     words = pack_flags(bits)
     if garbage_padding and N % 32:
         pad = ~np.uint32((1 << (N % 32)) - 1)
-        junk = rng.integers(0, 2 ** 32, (T, F), dtype=np.uint32) & pad
+        junk = rng.integers(0, 2 ** 32, (F, T), dtype=np.uint32) & pad
         words[:, :, -1] |= junk
     return words
 
@@ -213,7 +215,7 @@ def random_flags(rng: np.random.Generator, T: int, F: int, N: int,
     words = pack_flags(rng.random((T, F, N)) < p)
     if garbage_padding and N % 32:
         pad = ~np.uint32((1 << (N % 32)) - 1)
-        words[:, :, -1] |= rng.integers(0, 2 ** 32, (T, F), dtype=np.uint32) & pad
+        words[:, :, -1] |= rng.integers(0, 2 ** 32, (F, T), dtype=np.uint32) & pad
     return words
 
 

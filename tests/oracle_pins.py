@@ -329,8 +329,8 @@ def _flag_case(seed, N=37, F=3, T=70, B=8, p=0.25, p_loss=0.2):
     packed = _frame_from_values(re, im)
     mask = synth.bernoulli_mask(rng, F, T, B, p_loss)
     flags = synth.random_flags(rng, T, F, N, p, garbage_padding=True)
-    flags[3, 1, :] = 0xFFFFFFFF
-    flags[5, :, 0] = 0
+    flags[1, 3, :] = 0xFFFFFFFF
+    flags[:, 5, 0] = 0
     return re, im, packed, mask, flags, B
 
 
@@ -360,8 +360,8 @@ def pin_flag_counts_brute_force(orc):
         # two halves of a frame (split on a block edge) add up to the whole
         h = (T // 2) // B * B
         if 0 < h < T:
-            c2, d2 = orc.flag_counters(flags[:h], mask[:, :h // B], N, B)
-            orc.flag_counters(flags[h:], mask[:, h // B:], N, B, c2, d2)
+            c2, d2 = orc.flag_counters(flags[:, :h], mask[:, :h // B], N, B)
+            orc.flag_counters(flags[:, h:], mask[:, h // B:], N, B, c2, d2)
             assert (c2 == c).all() and (d2 == d).all(), seed
 
 

@@ -50,7 +50,7 @@ MUTANTS = [
     ("flag_norm_intersection_sign", "+ d[p];", "- d[p];", 1),
     ("flag_norm_one_counter", " - c[(int64_t)f * N + j] + d[p];", " + d[p];", 1),
     ("flag_zero_byte", "= 0x88;", "= 0x00;", 1),
-    ("flagged_one_side", "(input_flagged(flags, N, F, f, t, i) ||\n", "(0 ||\n", 1),
+    ("flagged_one_side", "(input_flagged(flags, N, T, f, t, i) ||\n", "(0 ||\n", 1),
     ("flag_word_bit", "i / 32] >> (i % 32))", "i / 32] >> (31 - i % 32))", 1),
     ("normalize_pairs_float",
      "(float)((double)vis[2 * q + k] / (double)m)", "(float)vis[2 * q + k] / (float)m", 1),
