@@ -115,6 +115,52 @@ xe_status xe_accumulate(xe_handle h, const uint8_t *packed,
 xe_status xe_normalize(xe_handle h, const int32_t *vis, const int64_t *count,
                        int32_t N, int32_t F, float *out, void *stream);
 
+/* Per-input flags (Sec. II-C).  Besides lost packets, the F-engine flags
+ * single data points (range and sampling faults).  They arrive as
+ * bit-fields `flags`, uint32 [F][T][ceil(N/32)] (channel-major): bit i % 32
+ * of word i / 32 is set when input i is flagged at that channel and sample;
+ * bits past input N-1 in the last word are ignored.  Flagged points are
+ * zeroed before correlation (xe_apply_flags), so baseline (i, j) integrates
+ *     n_ij = count[f] - c_i - c_j + d_ij
+ * samples, c_i = valid samples with i flagged, d_ij = valid samples with
+ * both flagged (the method's per-input counters and per-sample
+ * intersections).  All three calls take device pointers and are
+ * capture-safe (kernels only). */
+
+/* ADD the flag intersections of one frame into dcount, int32 [F][P], the
+ * same packed upper triangle as vis: entry (i, j), i < j, counts the valid
+ * samples where inputs i and j are both flagged; the diagonal entry (i, i)
+ * counts those where input i is flagged (c_i).  Samples in lost blocks of
+ * loss_mask (may be NULL) are not counted: their packet, footer included,
+ * never arrived.  Computed on the matrix cores as a 0/1 Gram matrix per
+ * channel over time; steps and blocks without flags are skipped.  Limits as
+ * for xe_accumulate; flags and dcount 4-byte aligned.  Counts from several
+ * frames add up exactly (integer sums). */
+xe_status xe_flag_accumulate(xe_handle h, const uint32_t *flags,
+                             const uint8_t *loss_mask, int32_t N, int32_t F,
+                             int32_t T, int32_t B, int32_t *dcount,
+                             void *stream);
+
+/* Zero every flagged point of a frame in place: the byte becomes 0x88,
+ * i.e. 0 + 0i (Sec. II-C: flagged data points are zeroed before they
+ * reach the correlator).  Unflagged bytes are not written.  flags 4-byte
+ * aligned; packed [T][F][N] as for xe_accumulate. */
+xe_status xe_apply_flags(xe_handle h, uint8_t *packed, const uint32_t *flags,
+                         int32_t N, int32_t F, int32_t T, void *stream);
+
+/* out[f][p] = (float)((double)vis / (double)n_ij) per baseline (re and im),
+ * rounded once to nearest; 0 where n_ij == 0, with
+ *     n_ij = count[f] - dcount[f][(i,i)] - dcount[f][(j,j)] + dcount[f][(i,j)]
+ * (Sec. II-C: the normalisation matrix, applied to the correlation matrix
+ * at the end of an integration).  n_out (may be NULL) receives n_ij, int32
+ * [F][P].  vis, count and dcount must cover the same frames, so that
+ * n_ij >= 0.  vis, count, out and n_out 8-byte aligned (n_out 4), dcount
+ * 4-byte aligned; out may not overlap vis or dcount. */
+xe_status xe_normalize_flagged(xe_handle h, const int32_t *vis,
+                               const int64_t *count, const int32_t *dcount,
+                               int32_t N, int32_t F, float *out,
+                               int32_t *n_out, void *stream);
+
 /* One correlator instance of a batch: a frame of one sub-array with its own
  * N, F, T and B, accumulated into its own vis and count.  Pointers are
  * device pointers; the array of instances itself is host memory. */

@@ -14,6 +14,7 @@
 #include "../../include/xengine.h"
 #include "plan.hpp"
 #include "xcorr_kernels.hpp"
+#include "flag_kernels.hpp"
 
 // Batch plans live in a device area allocated with the handle: kRingSlots
 // slots that xe_accumulate_batch cycles through (each guarded by an event,
@@ -389,6 +390,52 @@ xe_status launch_batch(xe_handle h, int slot, const SlotShape &sh, hipStream_t s
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// per-input flags
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Work split of the flag Gram kernel: (channel, super-block pair, time
+// chunk); chunks of at least 4 stages, about two workgroups per compute unit.
+xe::flag::Args flag_args(const uint32_t *flags, const uint8_t *mask, int32_t N, int32_t F,
+                         int32_t T, int32_t B, int32_t *d, int n_cu) {
+    using namespace xe::flag;
+    Args a{};
+    a.flags = flags;
+    a.mask = mask;
+    a.d = d;
+    a.N = N;
+    a.F = F;
+    a.T = T;
+    a.B = B;
+    a.W = (N + 31) / 32;
+    a.nblk = (T + B - 1) / B;
+    a.ns = (N + 255) / 256;
+    const int64_t units = (int64_t)F * (a.ns * (a.ns + 1) / 2);
+    const int64_t stages = (T + kStage - 1) / kStage;
+    int64_t want = (2 * (int64_t)std::max(n_cu, 1) + units - 1) / units;
+    const int64_t most = std::max<int64_t>(1, stages / 4);
+    want = std::min(std::max<int64_t>(want, 1), most);
+    const int64_t per = (stages + want - 1) / want;
+    a.chunks = (int)((stages + per - 1) / per);
+    a.chunk_samples = (int)(per * kStage);
+    a.b_magic = B <= 65536 ? (((uint64_t)1 << 40) + (uint64_t)B - 1) / (uint64_t)B : 0;
+    return a;
+}
+
+xe_status check_flags(xe_handle h, const uint32_t *flags, int32_t N, int32_t F, int32_t T,
+                      int32_t B) {
+    if (!h) return XE_ERR_ARG;
+    xe_status s = check_shape(h, N, F, T, B);
+    if (s != XE_OK) return s;
+    if (!flags) return fail(h, XE_ERR_ARG, "null pointer");
+    if (!aligned(flags, 4)) return fail(h, XE_ERR_ALIGN, "flags not 4-byte aligned");
+    return XE_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 xe_status xe_create(xe_handle *out, int32_t hip_device, size_t workspace_bytes) {
@@ -542,6 +589,86 @@ xe_status xe_normalize(xe_handle h, const int32_t *vis, const int64_t *count, in
                            (hipStream_t)stream, vis, count, out, per, F);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "normalize launch");
+    return XE_OK;
+}
+
+xe_status xe_flag_accumulate(xe_handle h, const uint32_t *flags, const uint8_t *loss_mask,
+                             int32_t N, int32_t F, int32_t T, int32_t B, int32_t *dcount,
+                             void *stream) {
+    xe_status s = check_flags(h, flags, N, F, T, B);
+    if (s != XE_OK) return s;
+    if (!dcount) return fail(h, XE_ERR_ARG, "null pointer");
+    if (!aligned(dcount, 4)) return fail(h, XE_ERR_ALIGN, "dcount not 4-byte aligned");
+    if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
+    xe::flag::Args a = flag_args(flags, loss_mask, N, F, T, B, dcount, h->n_cu);
+    const int64_t diag_blocks = (int64_t)F * a.ns * a.chunks;
+    const int64_t off_blocks = (int64_t)F * (a.ns * (a.ns - 1) / 2) * a.chunks;
+    hipLaunchKernelGGL(xe::flag::gram_kernel<false>, dim3((unsigned)diag_blocks),
+                       dim3(xe::flag::kThreads), 0, (hipStream_t)stream, a);
+    if (off_blocks > 0)
+        hipLaunchKernelGGL(xe::flag::gram_kernel<true>, dim3((unsigned)off_blocks),
+                           dim3(xe::flag::kThreads), 0, (hipStream_t)stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "flag gram launch");
+    return XE_OK;
+}
+
+xe_status xe_apply_flags(xe_handle h, uint8_t *packed, const uint32_t *flags, int32_t N,
+                         int32_t F, int32_t T, void *stream) {
+    xe_status s = check_flags(h, flags, N, F, T, 1);
+    if (s != XE_OK) return s;
+    if (!packed) return fail(h, XE_ERR_ARG, "null pointer");
+    const int W = (N + 31) / 32;
+    const char *pb = (const char *)packed, *fb = (const char *)flags;
+    const int64_t pbytes = (int64_t)T * F * N, fbytes = (int64_t)F * T * W * 4;
+    if (pb < fb + fbytes && fb < pb + pbytes) return fail(h, XE_ERR_ARG, "packed and flags overlap");
+    if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
+    const int64_t total = (int64_t)F * T * W;
+    int64_t blocks = std::min<int64_t>((total + 255) / 256, 8192);
+    if (N % 32 == 0 && aligned(packed, 16))
+        hipLaunchKernelGGL(xe::flag::apply_kernel<true>, dim3((unsigned)blocks), dim3(256), 0,
+                           (hipStream_t)stream, packed, flags, N, F, T, W);
+    else
+        hipLaunchKernelGGL(xe::flag::apply_kernel<false>, dim3((unsigned)blocks), dim3(256), 0,
+                           (hipStream_t)stream, packed, flags, N, F, T, W);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "apply flags launch");
+    return XE_OK;
+}
+
+xe_status xe_normalize_flagged(xe_handle h, const int32_t *vis, const int64_t *count,
+                               const int32_t *dcount, int32_t N, int32_t F, float *out,
+                               int32_t *n_out, void *stream) {
+    if (!h) return XE_ERR_ARG;
+    xe_status s = check_shape(h, N, F, 1, 1);
+    if (s != XE_OK) return s;
+    if (!vis || !count || !dcount || !out) return fail(h, XE_ERR_ARG, "null pointer");
+    if (!aligned(vis, 8) || !aligned(count, 8) || !aligned(out, 8) || !aligned(dcount, 4) ||
+        (n_out && !aligned(n_out, 4)))
+        return fail(h, XE_ERR_ALIGN, "vis/count/out not 8-byte or dcount/n_out not 4-byte aligned");
+    const int64_t P = (int64_t)N * (N + 1) / 2;
+    auto overlap = [](const void *a, int64_t na, const void *b, int64_t nb) {
+        const char *x = (const char *)a, *y = (const char *)b;
+        return x < y + nb && y < x + na;
+    };
+    if (overlap(out, P * F * 8, vis, P * F * 8) || overlap(out, P * F * 8, dcount, P * F * 4) ||
+        (n_out && (overlap(n_out, P * F * 4, vis, P * F * 8) ||
+                   overlap(n_out, P * F * 4, dcount, P * F * 4) ||
+                   overlap(n_out, P * F * 4, out, P * F * 8))))
+        return fail(h, XE_ERR_ARG, "outputs overlap inputs");
+    if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
+    const int64_t total = P * F;
+    int64_t blocks = std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(xe::flag::normalize_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       (hipStream_t)stream, vis, count, dcount, out, n_out, N, F);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "normalize flagged launch");
     return XE_OK;
 }
 

@@ -33,7 +33,8 @@ XE_DEVICE_NONE = -1
 EXPORTS = ("xe_create", "xe_destroy", "xe_status_string", "xe_last_error",
            "xe_correlate_frame", "xe_accumulate", "xe_normalize",
            "xe_accumulate_batch", "xe_batch_plan", "xe_batch_run", "xe_batch_release",
-           "xe_batch_query", "xe_plan_query")
+           "xe_batch_query", "xe_plan_query",
+           "xe_flag_accumulate", "xe_apply_flags", "xe_normalize_flagged")
 
 
 class XEngineUnavailable(RuntimeError):
@@ -96,6 +97,12 @@ def lib() -> ctypes.CDLL:
                 fn.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp, vp]
             L.xe_normalize.restype = i32
             L.xe_normalize.argtypes = [vp, vp, vp, i32, i32, vp, vp]
+            L.xe_flag_accumulate.restype = i32
+            L.xe_flag_accumulate.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp]
+            L.xe_apply_flags.restype = i32
+            L.xe_apply_flags.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+            L.xe_normalize_flagged.restype = i32
+            L.xe_normalize_flagged.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
             L.xe_accumulate_batch.restype = i32
             L.xe_accumulate_batch.argtypes = [vp, ctypes.POINTER(Instance), i32, vp]
             L.xe_batch_plan.restype = i32
@@ -262,6 +269,88 @@ def normalize(vis, count, out=None, handle: Optional[Handle] = None, stream=None
     h.check(lib().xe_normalize(h.ptr, ctypes.c_void_p(vis.data_ptr()),
                                ctypes.c_void_p(count.data_ptr()), N, F,
                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+# -- per-input flags (Sec. II-C) ---------------------------------------------
+
+def _check_flags(flags, F, T, N):
+    import torch
+    W = (N + 31) // 32
+    if flags.dtype != torch.int32 or tuple(flags.shape) != (F, T, W) or \
+            not flags.is_cuda or not flags.is_contiguous():
+        raise ValueError(f"flags must be a contiguous CUDA int32 tensor [{F}, {T}, {W}] "
+                         "holding the uint32 bit-fields")
+
+
+def new_flag_counts(N: int, F: int, device=None):
+    """Zeroed int32 [F, P] intersection counts for flag_accumulate."""
+    import torch
+    dev = device if device is not None else torch.device("cuda")
+    return torch.zeros((F, N * (N + 1) // 2), dtype=torch.int32, device=dev)
+
+
+def flag_accumulate(flags, mask, B: int, N: int, dcount, handle: Optional[Handle] = None,
+                    stream=None):
+    """dcount += per-baseline flag intersections of one frame (diagonal: the
+    per-input flag counters); ``flags`` int32 [F, T, ceil(N/32)] bit-fields."""
+    import torch
+    F, T = int(flags.shape[0]), int(flags.shape[1])
+    _check_flags(flags, F, T, N)
+    if mask is not None:
+        nblk = (T + B - 1) // B
+        if mask.dtype != torch.uint8 or tuple(mask.shape) != (F, nblk) or \
+                not mask.is_cuda or not mask.is_contiguous():
+            raise ValueError(f"mask must be a contiguous CUDA uint8 tensor [{F}, {nblk}]")
+    P = N * (N + 1) // 2
+    if dcount.dtype != torch.int32 or tuple(dcount.shape) != (F, P) or \
+            not dcount.is_contiguous():
+        raise ValueError(f"dcount must be contiguous int32 [{F}, {P}]")
+    h = handle or default_handle(flags.device.index)
+    h.check(lib().xe_flag_accumulate(
+        h.ptr, ctypes.c_void_p(flags.data_ptr()),
+        ctypes.c_void_p(mask.data_ptr() if mask is not None else None),
+        N, F, T, B, ctypes.c_void_p(dcount.data_ptr()), _stream_ptr(stream)))
+    return dcount
+
+
+def apply_flags(packed, flags, handle: Optional[Handle] = None, stream=None):
+    """Zero the flagged points of ``packed`` in place (byte 0x88)."""
+    T, F, N = _check_frame(packed, None, 1)
+    _check_flags(flags, F, T, N)
+    h = handle or default_handle(packed.device.index)
+    h.check(lib().xe_apply_flags(h.ptr, ctypes.c_void_p(packed.data_ptr()),
+                                 ctypes.c_void_p(flags.data_ptr()), N, F, T,
+                                 _stream_ptr(stream)))
+    return packed
+
+
+def normalize_flagged(vis, count, dcount, out=None, n_out=None,
+                      handle: Optional[Handle] = None, stream=None):
+    """float32 V / n_ij per baseline, n_ij = count - d_ii - d_jj + d_ij
+    (0 where n_ij == 0); ``n_out`` (optional int32 [F, P]) receives n_ij."""
+    import torch
+    F, P, two = vis.shape
+    N = int(round(((8 * P + 1) ** 0.5 - 1) / 2))
+    if two != 2 or N * (N + 1) // 2 != P:
+        raise ValueError("vis must be [F, N(N+1)/2, 2]")
+    _check_acc(vis, count, N, F)
+    if dcount.dtype != torch.int32 or tuple(dcount.shape) != (F, P) or \
+            not dcount.is_contiguous():
+        raise ValueError(f"dcount must be contiguous int32 [{F}, {P}]")
+    if out is None:
+        out = torch.empty((F, P, 2), dtype=torch.float32, device=vis.device)
+    if out.dtype != torch.float32 or tuple(out.shape) != (F, P, 2) or not out.is_contiguous():
+        raise ValueError("out must be contiguous float32 [F, P, 2]")
+    if n_out is not None and (n_out.dtype != torch.int32 or tuple(n_out.shape) != (F, P)
+                              or not n_out.is_contiguous()):
+        raise ValueError("n_out must be contiguous int32 [F, P]")
+    h = handle or default_handle(vis.device.index)
+    h.check(lib().xe_normalize_flagged(
+        h.ptr, ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(count.data_ptr()),
+        ctypes.c_void_p(dcount.data_ptr()), N, F, ctypes.c_void_p(out.data_ptr()),
+        ctypes.c_void_p(n_out.data_ptr() if n_out is not None else None),
+        _stream_ptr(stream)))
     return out
 
 

@@ -226,3 +226,38 @@ def test_tile_groups_cover_the_triangle_once():
         tiles = [t for t in allt if t[0] < nb and t[1] < nb]
         want = [(i, j) for i in range(nb) for j in range(i, nb)]
         assert sorted(tiles) == want, nb
+
+
+def test_flag_checks(L, h):
+    def acc(flags=0x1000, mask=None, N=40, F=2, T=64, B=16, d=0x200000, hh=h):
+        return L.xe_flag_accumulate(hh, ctypes.c_void_p(flags), ctypes.c_void_p(mask), N, F,
+                                    T, B, ctypes.c_void_p(d), None)
+    assert acc() == xe.XE_ERR_NO_DEVICE
+    assert acc(hh=None) == xe.XE_ERR_ARG
+    for bad in (dict(flags=0), dict(d=0), dict(N=0), dict(F=0), dict(T=0), dict(B=0)):
+        assert acc(**bad) == xe.XE_ERR_ARG, bad
+    assert acc(flags=0x1002) == xe.XE_ERR_ALIGN
+    assert acc(d=0x200002) == xe.XE_ERR_ALIGN
+    assert acc(T=xe.XE_MAX_SAMPLES + 1) == xe.XE_ERR_OVERFLOW
+
+    def app(packed=0x100000, flags=0x1000, N=40, F=2, T=64):
+        return L.xe_apply_flags(h, ctypes.c_void_p(packed), ctypes.c_void_p(flags), N, F, T,
+                                None)
+    assert app() == xe.XE_ERR_NO_DEVICE
+    assert app(packed=0) == xe.XE_ERR_ARG
+    assert app(flags=0x1001) == xe.XE_ERR_ALIGN
+    assert app(packed=0x1000 + 64) == xe.XE_ERR_ARG   # overlaps the flags
+
+    def nrm(vis=0x100000, count=0x200000, d=0x300000, out=0x400000, n_out=None, N=40, F=2):
+        return L.xe_normalize_flagged(h, ctypes.c_void_p(vis), ctypes.c_void_p(count),
+                                      ctypes.c_void_p(d), N, F, ctypes.c_void_p(out),
+                                      ctypes.c_void_p(n_out), None)
+    assert nrm() == xe.XE_ERR_NO_DEVICE
+    assert nrm(n_out=0x500000) == xe.XE_ERR_NO_DEVICE
+    for bad in (dict(vis=0), dict(count=0), dict(d=0), dict(out=0), dict(N=0)):
+        assert nrm(**bad) == xe.XE_ERR_ARG, bad
+    assert nrm(out=0x100000 + 8) == xe.XE_ERR_ARG      # out overlaps vis
+    assert nrm(n_out=0x300000) == xe.XE_ERR_ARG        # n_out overlaps dcount
+    assert nrm(vis=0x100004) == xe.XE_ERR_ALIGN
+    assert nrm(d=0x300002) == xe.XE_ERR_ALIGN
+    assert nrm(n_out=0x500002) == xe.XE_ERR_ALIGN
