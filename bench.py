@@ -20,6 +20,10 @@ Prints ONE JSON line.  Fields beyond the common ones:
                 65536 samples) in one persistent launch replayed from a
                 captured graph, against the same instances as plain
                 per-instance launches; results compared bit for bit
+  flags         per-input flags on the same frame: the flag Gram kernel
+                (bursty 0.1% flags, and 50% as a stress case) against HBM,
+                the zeroing and per-baseline normalisation kernels, and the
+                flagged step against the plain one
   serving       8 streams of 4096-sample frames offered with Poisson
                 arrivals at 51.2 Gb/s in total from pinned host memory:
                 p50/p99 frame latency (arrival to accumulated); plus the
@@ -175,6 +179,84 @@ def batched_leg(torch, reps: int):
     }
 
 
+def flags_leg(torch, reps: int):
+    """Per-input flags on the pathfinder frame: the flag Gram kernel
+    (xe_flag_accumulate) with bursty F-engine flags at 0.1% of points (runs
+    of 32 samples) and, as a stress case, independent flags at 50%; the
+    zeroing and per-baseline normalisation kernels; and the whole flagged
+    step against the unflagged one.  The Gram kernel's HBM roofline counts
+    the flag words read once plus the counts read and written once."""
+    import numpy as np
+    from paper_1503_06189_amd import synth, xengine
+    dev = torch.device("cuda:0")
+    h = xengine.default_handle(0)
+    stream = torch.cuda.current_stream()
+    fr = synth.pathfinder()
+    N, F, T, B = fr.N, fr.F, fr.T, fr.B
+    rng = np.random.default_rng(2024)
+    bursty = synth.fengine_flags(rng, T, F, N, 1e-3, mean_run=32.0)
+    dense = synth.random_flags(rng, T, F, N, 0.5, garbage_padding=False)
+
+    def to_dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev)
+
+    fl_b, fl_d = to_dev(bursty), to_dev(dense)
+    packed = torch.from_numpy(fr.packed).to(dev)
+    mask = torch.from_numpy(fr.mask).to(dev)
+    vis, cnt = xengine.new_accumulators(N, F, dev)
+    dcount = xengine.new_flag_counts(N, F, dev)
+    out = torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.float32, device=dev)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch, 2)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    gram_b = timed(lambda: xengine.flag_accumulate(fl_b, mask, B, N, dcount, handle=h,
+                                                   stream=stream))
+    gram_d = timed(lambda: xengine.flag_accumulate(fl_d, mask, B, N, dcount, handle=h,
+                                                   stream=stream))
+    apply_b = timed(lambda: xengine.apply_flags(packed, fl_b, handle=h, stream=stream))
+    norm = timed(lambda: xengine.normalize_flagged(vis, cnt, dcount, out=out, handle=h,
+                                                   stream=stream))
+
+    def flagged_step():
+        xengine.apply_flags(packed, fl_b, handle=h, stream=stream)
+        xengine.accumulate(packed, mask, B, vis, cnt, handle=h, stream=stream)
+        xengine.flag_accumulate(fl_b, mask, B, N, dcount, handle=h, stream=stream)
+        xengine.normalize_flagged(vis, cnt, dcount, out=out, handle=h, stream=stream)
+
+    def plain_step():
+        xengine.accumulate(packed, mask, B, vis, cnt, handle=h, stream=stream)
+        xengine.normalize(vis, cnt, out, handle=h, stream=stream)
+
+    step_f = timed(flagged_step)
+    step_p = timed(plain_step)
+    flag_bytes = F * T * synth.flag_words(N) * 4
+    d_bytes = 2 * F * (N * (N + 1) // 2) * 4
+    gbps = (flag_bytes + d_bytes) / (gram_b / 1e3) / 1e9
+    return {
+        "workload": f"{fr.name}, bursty flags 0.1% of points (runs of 32 samples)",
+        "flag_gram_us": round(gram_b * 1e3, 2),
+        "flag_gram_dense50_us": round(gram_d * 1e3, 2),
+        "apply_flags_us": round(apply_b * 1e3, 2),
+        "normalize_flagged_us": round(norm * 1e3, 2),
+        "flagged_step_ms": round(step_f, 4),
+        "plain_step_ms": round(step_p, 4),
+        "flag_gram_roofline": {"bound": "hbm", "achieved": round(gbps, 1),
+                               "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                               "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                               "alg_bytes": flag_bytes + d_bytes},
+    }
+
+
 def serving_leg(torch, seconds: float):
     from paper_1503_06189_amd import serve, synth
     specs = synth.streaming_streams()
@@ -210,6 +292,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-flags", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 256 MiB once (a kernel of known "
@@ -314,6 +397,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         res["batched"] = batched_leg(torch, reps=max(3, min(20, args.steps)))
+        torch.cuda.empty_cache()
+    if not args.no_flags:
+        res["flags"] = flags_leg(torch, reps=max(5, min(50, args.steps)))
         torch.cuda.empty_cache()
     if not args.no_serving:
         res["serving"] = serving_leg(torch, args.serve_seconds)

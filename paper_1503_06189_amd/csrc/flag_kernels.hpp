@@ -16,7 +16,7 @@
 // of word i / 32 = input i.  A workgroup takes one channel, one pair of
 // 256-input super blocks (R <= C) and one chunk of time, in stages of 256
 // samples:
-//   1. the words of both super blocks are loaded two stages ahead (0 for
+//   1. the words of both super blocks are loaded several stages ahead (0 for
 //      lost samples, samples past the chunk and inputs past N) and stored in
 //      LDS with one "any flag" bit per (32-input block, 32-sample step),
 //      gathered by wave ballots;
@@ -48,7 +48,7 @@ constexpr int kSuper = 8;                // 32-input blocks per super block
 constexpr int kSteps = 8;                // 32-sample steps per stage
 constexpr int kStage = kSteps * 32;      // samples per stage
 constexpr int kPitch = kStage + 4;       // LDS words per block row (16-B aligned rows)
-constexpr int kLoads = kStage * kSuper / kThreads;  // flag words per thread, stage and side
+constexpr int kWindow = 2048;            // validity words per chunk: chunks <= 65536 samples
 
 struct Args {
     const uint32_t *flags;   // [F][T][W]
@@ -57,7 +57,7 @@ struct Args {
     int N, F, T, B, W, nblk;
     int ns;                  // super blocks, ceil(N / 256)
     int chunks;              // time chunks per (channel, pair)
-    int chunk_samples;       // samples per chunk, a multiple of kStage
+    int chunk_samples;       // samples per chunk, a multiple of kStage, <= 32 kWindow
     uint64_t b_magic;        // ceil(2^40 / B) when B <= 2^16, else 0
 };
 
@@ -102,6 +102,7 @@ struct Lds {
     uint32_t words[SIDES][kSuper][kPitch];      // [side][block][sample]
     v4i ops[SIDES][kSuper][kSteps][64];         // [side][block][step][lane]
     uint64_t any[2][SIDES][kWaves];             // [stage % 2][side][wave]: bit 8 b + s
+    uint32_t valid[kWindow];                    // bit k of word s: sample 32 s + k of the chunk
 };
 
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
@@ -110,14 +111,6 @@ __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel)
 
 __device__ __forceinline__ v16i mfma(v4i a, v4i b, v16i c) {
     return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
-}
-
-// bit k of an 8-bit value -> bit 8 k
-__device__ __forceinline__ uint64_t spread8(uint64_t x) {
-    x = (x | (x << 28)) & 0x0000000F0000000Full;
-    x = (x | (x << 14)) & 0x0003000300030003ull;
-    x = (x | (x << 7)) & 0x0101010101010101ull;
-    return x;
 }
 
 // Operand of (side, block b, step s) for this lane: byte q of the 16 is the
@@ -146,81 +139,114 @@ __device__ __forceinline__ int64_t tri(int64_t N, int64_t i, int64_t j) {
     return i * N - i * (i - 1) / 2 + (j - i);
 }
 
-// Flag words of one stage, raw, in registers: element e = tid + 512 r is
-// sample e / 8 of the stage, word e % 8 of the super block.  Every load is
-// issued unconditionally from a clamped, in-range address and nothing is
-// computed from the loaded values until the stage is stored two stages
-// later (a load under a divergent branch, or arithmetic on its result, would
-// be waited for right away).
-// The loss byte of a sample's block is read as the aligned dword holding
-// it (the same page as the byte, so always mapped) and picked out at store
-// time.
+// Validity of the chunk's samples, one bit each, in LDS: 1 inside the chunk
+// and outside lost blocks.  All threads take part; a barrier must follow.
 template <int SIDES>
-struct StageRegs {
-    uint32_t w[SIDES][kLoads];
-    uint32_t lost[kLoads];     // dword holding the block's loss byte
-};
-
-// byte offset of the loss byte of sample tc of channel f from the 4-aligned
-// address just below the mask (0 without a mask)
-__device__ __forceinline__ int64_t mask_byte(const Args &a, int f, int tc) {
-    if (a.mask == nullptr) return 0;
-    const int64_t mis = (int64_t)((uintptr_t)a.mask & 3u);
-    return mis + (int64_t)f * a.nblk + block_of(a, tc);
+__device__ __forceinline__ void fill_window(const Args &a, Lds<SIDES> &L, int f, int t_begin,
+                                            int t_end, int tid) {
+    const int words = (t_end - t_begin + 31) >> 5;
+    for (int s = tid; s < words; s += kThreads) {
+        const int t = t_begin + 32 * s;
+        const int n = min(32, t_end - t);
+        uint32_t bits = n == 32 ? 0xffffffffu : (1u << n) - 1u;
+        if (a.mask) {
+            const uint8_t *row = a.mask + (int64_t)f * a.nblk;
+            for (int b = block_of(a, t), last = block_of(a, t + n - 1); b <= last; ++b) {
+                if (row[b] == 0) continue;
+                const int lo = max(t, b * a.B) - t;
+                const int hi = min(t + n, (b + 1) * a.B) - t;        // exclusive
+                const uint64_t span = ((1ull << hi) - 1ull) & ~((1ull << lo) - 1ull);
+                bits &= ~(uint32_t)span;
+            }
+        }
+        L.valid[s] = bits;
+    }
 }
 
+// Flag words of one stage, raw, in registers.  Thread tid owns sample
+// tid / 2 of the stage and words 4 (tid % 2) .. +3 of each super block, so
+// wave w covers step w.  The words are read through a buffer resource whose
+// range ends at the chunk's last sample: loads past it return 0 without a
+// memory access, so every load is issued unconditionally, and nothing is
+// computed from the loaded values until the stage is stored D stages later
+// (arithmetic on a load's result would be waited for right away).
 template <int SIDES>
-__device__ __forceinline__ void load_stage(const Args &a, StageRegs<SIDES> &g, int f, int R,
-                                           int C, int t0, int tid) {
-    // dwords of the mask, from the 4-aligned address at or below its start
-    // (the flags stand in when there is no mask; the value is then unused)
-    const uint32_t *mwords =
-        a.mask ? (const uint32_t *)(a.mask - ((uintptr_t)a.mask & 3u)) : a.flags;
-    const uint32_t *frow = a.flags + (int64_t)f * a.T * a.W;
+struct StageRegs {
+    uint32_t w[SIDES][4];
+};
+
+// per-thread constants of the stage loop
+template <int SIDES>
+struct Lane {
+    __amdgpu_buffer_rsrc_t rsrc;   // the chunk's rows of this channel's flags
+    uint32_t row_bytes;            // 4 W
+    uint32_t off[SIDES][4];        // byte offset of each word in a row (word clamped to W - 1)
+    uint32_t pad[SIDES][4];        // bits of inputs < N
+    int smp;                       // sample within the stage
+    int k0;                        // first of the thread's 4 block rows
+};
+
+template <int SIDES>
+__device__ __forceinline__ Lane<SIDES> make_lane(const Args &a, int f, int R, int C,
+                                                 int t_begin, int t_end, int tid) {
+    Lane<SIDES> l;
+    l.smp = tid >> 1;
+    l.k0 = 4 * (tid & 1);
+    l.row_bytes = 4u * (uint32_t)a.W;
 #pragma unroll
-    for (int r = 0; r < kLoads; ++r) {
-        const int e = tid + kThreads * r;
-        const int tc = min(t0 + (e >> 3), a.T - 1);
-        g.lost[r] = mwords[mask_byte(a, f, tc) >> 2];
+    for (int side = 0; side < SIDES; ++side)
 #pragma unroll
-        for (int side = 0; side < SIDES; ++side) {
-            const int gw = (side == 0 ? R : C) * kSuper + (e & 7);
-            g.w[side][r] = frow[(int64_t)tc * a.W + min(gw, a.W - 1)];
+        for (int r = 0; r < 4; ++r) {
+            const int gw = (side == 0 ? R : C) * kSuper + l.k0 + r;
+            const int rest = a.N - gw * 32;
+            l.off[side][r] = 4u * (uint32_t)min(gw, a.W - 1);
+            l.pad[side][r] = rest >= 32 ? 0xffffffffu : rest > 0 ? (1u << rest) - 1u : 0u;
         }
-    }
+    // wave-uniform; readfirstlane keeps the resource in scalar registers
+    const uint64_t base = (uint64_t)(uintptr_t)(a.flags + ((int64_t)f * a.T + t_begin) * a.W);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+    const uint32_t extent =
+        __builtin_amdgcn_readfirstlane((uint32_t)(t_end - t_begin) * l.row_bytes);
+    void *p = (void *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+    l.rsrc = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)extent, 0x00020000);
+    return l;
+}
+
+// stage starting ts samples into the chunk; offsets stay below 2^31 (a chunk
+// holds at most 65536 samples of at most 512 bytes)
+template <int SIDES>
+__device__ __forceinline__ void load_stage(const Lane<SIDES> &l, StageRegs<SIDES> &g, int ts) {
+    const uint32_t row = (uint32_t)(ts + l.smp) * l.row_bytes;
+#pragma unroll
+    for (int side = 0; side < SIDES; ++side)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            g.w[side][r] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
+                l.rsrc, (int)(row + l.off[side][r]), 0, 0);
 }
 
 // Store a stage's words in LDS (0 for lost samples, samples past the chunk
 // and inputs past N) and publish, per wave, which (block, step) hold a flag:
-// the 64 lanes of one load cover 8 samples of one step and lane % 8 = block,
-// so a ballot folded over its 8 bytes gives the blocks.
+// a wave's 64 lanes are the 32 samples of one step, even lanes holding block
+// rows r and odd lanes rows 4 + r, so two masks of a ballot give the bits.
 template <int SIDES>
-__device__ __forceinline__ void store_stage(const Args &a, Lds<SIDES> &L,
-                                            const StageRegs<SIDES> &g, int f, int R, int C, int t0,
-                                            int t_end, int buf, int wave, int lane, int tid) {
-    const bool has_mask = a.mask != nullptr;
+__device__ __forceinline__ void store_stage(Lds<SIDES> &L, const Lane<SIDES> &l,
+                                            const StageRegs<SIDES> &g, int ts, int buf,
+                                            int wave, int lane) {
+    const int t = ts + l.smp;   // sample within the chunk
+    const uint32_t wv = t < 32 * kWindow ? L.valid[t >> 5] : 0u;
+    const uint32_t keep = 0u - ((wv >> (t & 31)) & 1u);
 #pragma unroll
     for (int side = 0; side < SIDES; ++side) {
         uint64_t any = 0;
 #pragma unroll
-        for (int r = 0; r < kLoads; ++r) {
-            const int e = tid + kThreads * r;
-            const int gw = (side == 0 ? R : C) * kSuper + (e & 7);
-            const int rest = a.N - gw * 32;
-            const uint32_t pad = rest >= 32 ? 0xffffffffu : rest > 0 ? (1u << rest) - 1u : 0u;
-            const int t = t0 + (e >> 3);
-            const int64_t mb = mask_byte(a, f, min(t, a.T - 1));
-            const uint32_t lost = (g.lost[r] >> (8 * (int)(mb & 3))) & 0xffu;
-            // branch-free: 0 past the chunk or in a lost block
-            const uint32_t keep = (uint32_t)(t < t_end) & (uint32_t)(!has_mask | (lost == 0u));
-            const uint32_t v = g.w[side][r] & pad & (0u - keep);
-            L.words[side][e & 7][e >> 3] = v;
-            uint64_t m = __ballot(v != 0u);
-            m |= m >> 32;
-            m |= m >> 16;
-            m |= m >> 8;
-            const int step = (wave + kWaves * r) >> 2;
-            any |= spread8(m & 0xffu) << step;
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t v = g.w[side][r] & l.pad[side][r] & keep;
+            L.words[side][l.k0 + r][l.smp] = v;
+            const uint64_t m = __ballot(v != 0u);
+            any |= (uint64_t)((m & 0x5555555555555555ull) != 0) << (r * 8 + wave);
+            any |= (uint64_t)((m & 0xAAAAAAAAAAAAAAAAull) != 0) << ((4 + r) * 8 + wave);
         }
         if (lane == 0) L.any[buf][side][wave] = any;
     }
@@ -244,18 +270,25 @@ __device__ __forceinline__ void run_role(const Args &a, Lds<SIDES> &L, int f, in
     }
 
     const int nst = (t_end - t_begin + kStage - 1) / kStage;
-    StageRegs<SIDES> g[2];
-    // Stage st's words sit in g[st % 2] from two stages ahead until stored.
-    // Loads and stores run for every stage, also past the chunk's end (in
-    // range, read as 0): the same number of loads on every path lets each
-    // store wait for its own loads only.
-    load_stage(a, g[0], f, R, C, t_begin, tid);
-    load_stage(a, g[1], f, R, C, t_begin + kStage, tid);
-    store_stage(a, L, g[0], f, R, C, t_begin, t_end, 0, wave, lane, tid);
-    load_stage(a, g[0], f, R, C, t_begin + 2 * kStage, tid);
+    const Lane<SIDES> ln = make_lane<SIDES>(a, f, R, C, t_begin, t_end, tid);
+    fill_window(a, L, f, t_begin, t_end, tid);
+    // Stage j's words sit in g[j % D] from D stages ahead until stored (D =
+    // 6 for a diagonal pair, 2 for the register-heavy off-diagonal roles).
+    // Loads and stores run for every stage, also past the chunk's end (out
+    // of the buffer's range: 0, no memory access), so that every path issues
+    // the same loads and each store waits for its own loads only.
+    constexpr int D = SIDES == 1 ? 6 : 2;
+    StageRegs<SIDES> g[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) load_stage(ln, g[j], j * kStage);
+    __syncthreads();  // validity window visible
+    store_stage(L, ln, g[0], 0, 0, wave, lane);
+    load_stage(ln, g[0], D * kStage);
 
-    auto stage = [&](int st, auto parity) {
-        constexpr int P = decltype(parity)::value;
+    auto stage = [&](int st, auto slot) {
+        constexpr int J = decltype(slot)::value;        // st % D
+        constexpr int P = J % 2;                        // st % 2 (D is even)
+        constexpr int JN = (J + 1) % D;                 // (st + 1) % D
         __syncthreads();  // words and flag bits of stage st visible
         uint64_t any0 = 0, any1 = 0;
 #pragma unroll
@@ -272,35 +305,38 @@ __device__ __forceinline__ void run_role(const Args &a, Lds<SIDES> &L, int f, in
                ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(any1 >> 32)) << 32);
         const bool work = any0 != 0 && any1 != 0;
         if (work) {
-            // operand builds: item q = 8 b + s, wave w takes q = w mod 8
+            // operand builds: wave w builds step w of all 8 blocks, every
+            // block when the step holds any flag (reads issued together, no
+            // wait per item); slots of flag-free blocks are never read below
+            constexpr uint64_t kCol = 0x0101010101010101ull;
 #pragma unroll
             for (int side = 0; side < SIDES; ++side) {
                 const uint64_t bits = side == 0 ? any0 : any1;
+                if (((bits >> wave) & kCol) != 0) {
 #pragma unroll
-                for (int m = 0; m < kSuper; ++m) {
-                    const int q = wave + kWaves * m;
-                    if ((bits >> q) & 1u) build_op(L, side, q >> 3, q & 7, lane);
+                    for (int b = 0; b < kSuper; ++b) build_op(L, side, b, wave, lane);
                 }
             }
             __syncthreads();  // operands visible
         }
         // this stage's words are done: store the next stage, load the one after
-        store_stage(a, L, g[1 - P], f, R, C, t_begin + (st + 1) * kStage, t_end, 1 - P, wave,
-                    lane, tid);
-        load_stage(a, g[1 - P], f, R, C, t_begin + (st + 3) * kStage, tid);
+        store_stage(L, ln, g[JN], (st + 1) * kStage, 1 - P, wave, lane);
+        load_stage(ln, g[JN], (st + 1 + D) * kStage);
         if (work) {
             // one step at a time keeps the operands of later steps out of
-            // registers (the 8-tile role holds 128 accumulators)
+            // registers (the 8-tile role holds 128 accumulators); a step
+            // without flags on either side is skipped, otherwise all its
+            // operands are read at once and only the MFMAs are conditional
+            constexpr uint64_t kCol = 0x0101010101010101ull;
 #pragma unroll 1
             for (int s = 0; s < kSteps; ++s) {
+                if (((any0 >> s) & kCol) == 0 || ((any1 >> s) & kCol) == 0) continue;
                 v4i ro[RL::NR];
                 v4i co[RL::NC > 0 ? RL::NC : 1];
 #pragma unroll
-                for (int r = 0; r < RL::NR; ++r)
-                    if ((any0 >> ((rb0 + r) * 8 + s)) & 1u) ro[r] = L.ops[0][rb0 + r][s][lane];
+                for (int r = 0; r < RL::NR; ++r) ro[r] = L.ops[0][rb0 + r][s][lane];
 #pragma unroll
-                for (int c = 0; c < RL::NC; ++c)
-                    if ((any1 >> ((cb0 + c) * 8 + s)) & 1u) co[c] = L.ops[sc][cb0 + c][s][lane];
+                for (int c = 0; c < RL::NC; ++c) co[c] = L.ops[sc][cb0 + c][s][lane];
 #pragma unroll
                 for (int k = 0; k < RL::NT; ++k) {
                     const int rbk = rb0 + RL::r(k), cbk = cb0 + RL::c(k);
@@ -314,9 +350,18 @@ __device__ __forceinline__ void run_role(const Args &a, Lds<SIDES> &L, int f, in
             }
         }
     };
-    for (int st = 0; st < nst; st += 2) {
+    static_assert(D % 2 == 0 && D <= 6, "ring depth");
+    for (int st = 0; st < nst; st += D) {
         stage(st, std::integral_constant<int, 0>{});
         if (st + 1 < nst) stage(st + 1, std::integral_constant<int, 1>{});
+        if constexpr (D > 2) {
+            if (st + 2 < nst) stage(st + 2, std::integral_constant<int, 2 % D>{});
+            if (st + 3 < nst) stage(st + 3, std::integral_constant<int, 3 % D>{});
+        }
+        if constexpr (D > 4) {
+            if (st + 4 < nst) stage(st + 4, std::integral_constant<int, 4 % D>{});
+            if (st + 5 < nst) stage(st + 5, std::integral_constant<int, 5 % D>{});
+        }
     }
 
     // add the counts into d: element v of a tile sits at
