@@ -80,6 +80,8 @@ class Oracle:
                                                  _p, _p]
         lib.oracle_normalize_pairs.restype = None
         lib.oracle_normalize_pairs.argtypes = [_p, _p, _i32, _i32, _p]
+        lib.oracle_assemble.restype = None
+        lib.oracle_assemble.argtypes = [_p, _i64, _i32, _i32, _i32, _i64, _i32, _p, _p, _p, _p]
 
     # -- helpers ---------------------------------------------------------
     @staticmethod
@@ -232,6 +234,27 @@ class Oracle:
         out = np.zeros((F, P, 2), dtype=np.float32)
         self._lib.oracle_normalize_pairs(_ptr(vis), _ptr(n), N, F, _ptr(out))
         return out
+
+    # -- frame assembly from packets (Sec. II-A) -----------------------------
+    def assemble(self, packets, N: int, n_streams: int, stream_base: int, seq0: int, T: int):
+        """(packed [T][F][N], mask [F][T/4], flags [F][T][W], stats [6]) from
+        packets uint8 [n][packet_bytes] in arrival order."""
+        packets = np.ascontiguousarray(packets, dtype=np.uint8)
+        W = (N + 31) // 32
+        pb = 16 + 32 * N + 128 * W
+        if packets.ndim != 2 or (packets.shape[0] and packets.shape[1] != pb):
+            raise ValueError(f"packets must be uint8 [n][{pb}]")
+        if T % 4:
+            raise ValueError("T must be a multiple of 4")
+        F = 8 * n_streams
+        # outputs start as garbage: the assembler must write every element
+        packed = np.full((T, F, N), 0x5A, dtype=np.uint8)
+        mask = np.full((F, T // 4), 7, dtype=np.uint8)
+        flags = np.full((F, T, W), 0xDEADBEEF, dtype=np.uint32)
+        stats = np.full(6, -1, dtype=np.int64)
+        self._lib.oracle_assemble(_ptr(packets), packets.shape[0], N, n_streams, stream_base,
+                                  seq0, T, _ptr(packed), _ptr(mask), _ptr(flags), _ptr(stats))
+        return packed, mask, flags, stats
 
 
 _cached: Optional[Oracle] = None

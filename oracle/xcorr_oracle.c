@@ -326,3 +326,102 @@ void oracle_normalize_pairs(const int64_t *vis, const int64_t *n, int32_t N,
             out[2 * q + k] = m == 0 ? 0.0f : (float)((double)vis[2 * q + k] / (double)m);
         }
 }
+
+/* ---------------------------------------------------------------------
+ * Frame assembly from UDP packets (Sec. II-A: the network thread places
+ * each packet's data by its sequence number; missing packets leave zeros,
+ * out-of-order packets go to their own place, duplicates are ignored).
+ *
+ * Packet layout (the paper's figure of it is not available; this one keeps
+ * its contents): a 16-byte header (uint64 sequence number, uint32 stream
+ * id, uint32 input count N), then the data of 4 samples x 8 bands x N
+ * inputs, one byte each, in that order, then the flag bit-fields of the 4 x
+ * 8 (sample, band) pairs, W = ceil(N/32) uint32 words each.  Stream
+ * stream_base + s carries channels 8 s .. 8 s + 7 of the frame; the packet
+ * with sequence number seq0 + k holds samples 4 k .. 4 k + 3.
+ *
+ * stats [6]: packets in the frame's window, outside it, of an unknown
+ * stream, with a wrong input count, placed, and (stream, slot) places left
+ * empty.  Duplicates = in window - placed.
+ * --------------------------------------------------------------------- */
+void oracle_assemble(const uint8_t *packets, int64_t n_packets, int32_t N,
+                     int32_t n_streams, int32_t stream_base, int64_t seq0,
+                     int32_t T, uint8_t *packed, uint8_t *mask,
+                     uint32_t *flags, int64_t *stats)
+{
+    const int S = 4, NB = 8;
+    int64_t W = ((int64_t)N + 31) / 32;
+    int64_t F = (int64_t)NB * n_streams;
+    int64_t slots = T / S;
+    int64_t pbytes = 16 + (int64_t)S * NB * N + (int64_t)S * NB * W * 4;
+    char *filled = (char *)calloc((size_t)(n_streams * slots), 1);
+    if (filled == NULL)
+        return;
+    for (int k = 0; k < 6; ++k)
+        stats[k] = 0;
+    /* every packet in arrival order */
+    for (int64_t p = 0; p < n_packets; ++p) {
+        const uint8_t *pkt = packets + p * pbytes;
+        uint64_t seq = 0;
+        uint32_t sid = 0, nin = 0;
+        for (int b = 0; b < 8; ++b)
+            seq |= (uint64_t)pkt[b] << (8 * b);
+        for (int b = 0; b < 4; ++b) {
+            sid |= (uint32_t)pkt[8 + b] << (8 * b);
+            nin |= (uint32_t)pkt[12 + b] << (8 * b);
+        }
+        if (nin != (uint32_t)N) {
+            stats[3] += 1;
+            continue;
+        }
+        int64_t s = (int64_t)sid - stream_base;
+        if (s < 0 || s >= n_streams) {
+            stats[2] += 1;
+            continue;
+        }
+        if (seq < (uint64_t)seq0 || seq - (uint64_t)seq0 >= (uint64_t)slots) {
+            stats[1] += 1;
+            continue;
+        }
+        stats[0] += 1;
+        int64_t k = (int64_t)(seq - (uint64_t)seq0);
+        if (filled[s * slots + k])
+            continue;          /* a duplicate: the first arrival stays */
+        filled[s * slots + k] = 1;
+        stats[4] += 1;
+        for (int smp = 0; smp < S; ++smp)
+            for (int b = 0; b < NB; ++b) {
+                int64_t t = k * S + smp, f = s * NB + b;
+                for (int i = 0; i < N; ++i)
+                    packed[(t * F + f) * N + i] = pkt[16 + ((int64_t)smp * NB + b) * N + i];
+                const uint8_t *fw = pkt + 16 + (int64_t)S * NB * N +
+                                    (((int64_t)smp * NB + b) * W) * 4;
+                for (int64_t w = 0; w < W; ++w) {
+                    uint32_t v = 0;
+                    for (int c = 0; c < 4; ++c)
+                        v |= (uint32_t)fw[w * 4 + c] << (8 * c);
+                    flags[(f * T + t) * W + w] = v;
+                }
+            }
+    }
+    /* places no packet reached: zeros in the data, no flags, block lost */
+    for (int64_t s = 0; s < n_streams; ++s)
+        for (int64_t k = 0; k < slots; ++k) {
+            int lost = !filled[s * slots + k];
+            stats[5] += lost;
+            for (int b = 0; b < NB; ++b) {
+                int64_t f = s * NB + b;
+                mask[f * slots + k] = (uint8_t)lost;
+                if (!lost)
+                    continue;
+                for (int smp = 0; smp < S; ++smp) {
+                    int64_t t = k * S + smp;
+                    for (int i = 0; i < N; ++i)
+                        packed[(t * F + f) * N + i] = 0x88;
+                    for (int64_t w = 0; w < W; ++w)
+                        flags[(f * T + t) * W + w] = 0;
+                }
+            }
+        }
+    free(filled);
+}

@@ -220,6 +220,98 @@ def random_flags(rng: np.random.Generator, T: int, F: int, N: int,
 
 
 # ---------------------------------------------------------------------------
+# UDP packets of the F-engine (Sec. II-A)
+# ---------------------------------------------------------------------------
+
+#: time samples and frequency bands per packet (Sec. II-A)
+PKT_SAMPLES = 4
+PKT_BANDS = 8
+#: header: uint64 sequence number, uint32 stream id, uint32 input count
+PKT_HEADER = 16
+
+
+def packet_bytes(N: int) -> int:
+    """Header + data [4][8][N] bytes + footer flags [4][8][ceil(N/32)] uint32."""
+    return PKT_HEADER + PKT_SAMPLES * PKT_BANDS * N + PKT_SAMPLES * PKT_BANDS * flag_words(N) * 4
+
+
+def packetize(packed: np.ndarray, flags: Optional[np.ndarray] = None,
+              stream_base: int = 0, seq0: int = 0) -> np.ndarray:
+    """Cut a frame into packets, uint8 [n_packets][packet_bytes], in time
+    order with the streams of one time slot next to each other.
+
+    Stream s carries channels 8 s .. 8 s + 7; packet k of stream s holds
+    samples 4 k .. 4 k + 3 of those channels with sequence number seq0 + k.
+    ``flags`` (uint32 [F][T][W], optional) fills the footers.
+    """
+    T, F, N = packed.shape
+    if T % PKT_SAMPLES or F % PKT_BANDS:
+        raise ValueError("T must be a multiple of 4 and F of 8")
+    W = flag_words(N)
+    S, n_slot = F // PKT_BANDS, T // PKT_SAMPLES
+    pb = packet_bytes(N)
+    out = np.zeros((n_slot * S, pb), dtype=np.uint8)
+    data = packed.reshape(n_slot, PKT_SAMPLES, S, PKT_BANDS, N).transpose(0, 2, 1, 3, 4)
+    out[:, PKT_HEADER:PKT_HEADER + PKT_SAMPLES * PKT_BANDS * N] = \
+        data.reshape(n_slot * S, -1)
+    if flags is not None:
+        fw = np.ascontiguousarray(flags, dtype="<u4").reshape(S, PKT_BANDS, n_slot,
+                                                              PKT_SAMPLES, W)
+        fw = fw.transpose(2, 0, 3, 1, 4).reshape(n_slot * S, -1)   # [k][s][4][8][W]
+        out[:, PKT_HEADER + PKT_SAMPLES * PKT_BANDS * N:] = fw.view(np.uint8)
+    hdr = np.zeros((n_slot * S, 2), dtype="<u8")
+    k = np.repeat(np.arange(n_slot, dtype=np.uint64), S)
+    sid = np.tile(np.arange(S, dtype=np.uint64), n_slot) + np.uint64(stream_base)
+    hdr[:, 0] = np.uint64(seq0) + k
+    hdr[:, 1] = sid | (np.uint64(N) << np.uint64(32))
+    out[:, :PKT_HEADER] = hdr.view(np.uint8).reshape(-1, PKT_HEADER)
+    return out
+
+
+def packet_header(pkt: np.ndarray):
+    """(seq, stream_id, n_inputs) of one packet."""
+    h = np.frombuffer(pkt[:PKT_HEADER].tobytes(), dtype="<u8")
+    return int(h[0]), int(h[1] & 0xffffffff), int(h[1] >> np.uint64(32))
+
+
+def network_faults(rng: np.random.Generator, packets: np.ndarray, p_drop: float = 0.01,
+                   p_dup: float = 0.005, window: int = 64, n_stray: int = 0,
+                   stray_seq: int = 1 << 40) -> np.ndarray:
+    """What UDP does to a packet stream: drop each packet with p_drop,
+    duplicate each with p_dup (the copy arrives up to ``window`` packets
+    later, before or after the jittered original, and carries a different
+    payload so that the rule "the first arrival wins" is visible), reorder by
+    jittering arrival positions within ``window``, and append ``n_stray``
+    packets from outside the frame (sequence numbers near ``stray_seq``).
+    Draw order: drops, duplicates, duplicate payload, jitter, strays."""
+    n = packets.shape[0]
+    keep = rng.random(n) >= p_drop
+    dup = (rng.random(n) < p_dup) & keep
+    rows = list(np.flatnonzero(keep))
+    pos = [float(i) for i in rows]
+    extra = []
+    for i in np.flatnonzero(dup):
+        copy = packets[i].copy()
+        copy[PKT_HEADER:] = rng.integers(0, 256, copy.size - PKT_HEADER, dtype=np.uint8)
+        extra.append(copy)
+        pos.append(float(i) + 1 + rng.uniform(0, window))
+    jitter = rng.uniform(0, window, len(rows))
+    for j in range(len(rows)):
+        pos[j] += jitter[j]
+    allp = [packets[i] for i in rows] + extra
+    for k in range(n_stray):
+        st = packets[k % max(n, 1)].copy() if n else np.zeros(packets.shape[1], np.uint8)
+        h = np.frombuffer(st[:PKT_HEADER].tobytes(), dtype="<u8").copy()
+        h[0] = np.uint64(stray_seq + k)
+        st[:PKT_HEADER] = h.view(np.uint8)
+        allp.append(st)
+        pos.append(rng.uniform(0, n))
+    order = np.argsort(np.array(pos), kind="stable")
+    out = np.stack([allp[i] for i in order]) if allp else packets[:0].copy()
+    return out
+
+
+# ---------------------------------------------------------------------------
 # generic helpers for tests
 # ---------------------------------------------------------------------------
 

@@ -442,6 +442,96 @@ def pin_flag_normalize(orc):
                 assert abs(got - exact) <= half_ulp * (1 + Fraction(1, 2 ** 28)), (f, p, k)
 
 
+# ---------------------------------------------------------------------------
+# frame assembly from packets (Sec. II-A)
+# ---------------------------------------------------------------------------
+
+def _assembly_case(seed, N=37, n_streams=3, T=64, base=5, seq0=1000):
+    rng = np.random.default_rng(seed)
+    F = 8 * n_streams
+    packed = rng.integers(0, 256, (T, F, N), dtype=np.uint8)
+    flags = synth.random_flags(rng, T, F, N, 0.2, garbage_padding=True)
+    pk = synth.packetize(packed, flags, stream_base=base, seq0=seq0)
+    return rng, packed, flags, pk
+
+
+def _brute_assemble(pk, N, n_streams, base, seq0, T):
+    """Arrival order, first packet per (stream, slot), written with numpy
+    slicing of each packet (no loop over bytes)."""
+    F = 8 * n_streams
+    W = (N + 31) // 32
+    packed = np.full((T, F, N), synth.ZERO_BYTE, dtype=np.uint8)
+    mask = np.ones((F, T // 4), dtype=np.uint8)
+    flags = np.zeros((F, T, W), dtype=np.uint32)
+    seen = set()
+    stats = [0] * 6
+    for p in pk:
+        seq, sid, nin = synth.packet_header(p)
+        if nin != N:
+            stats[3] += 1
+            continue
+        s = sid - base
+        if not 0 <= s < n_streams:
+            stats[2] += 1
+            continue
+        k = seq - seq0
+        if not 0 <= k < T // 4:
+            stats[1] += 1
+            continue
+        stats[0] += 1
+        if (s, k) in seen:
+            continue
+        seen.add((s, k))
+        stats[4] += 1
+        data = p[16:16 + 32 * N].reshape(4, 8, N)
+        packed[4 * k:4 * k + 4, 8 * s:8 * s + 8, :] = data
+        fw = p[16 + 32 * N:].view("<u4").reshape(4, 8, W)
+        flags[8 * s:8 * s + 8, 4 * k:4 * k + 4, :] = fw.transpose(1, 0, 2)
+        mask[8 * s:8 * s + 8, k] = 0
+    stats[5] = int(mask[::8].sum())
+    return packed, mask, flags, np.array(stats)
+
+
+def pin_assemble_roundtrip(orc):
+    """Packets cut from a frame, in order and shuffled, give the frame back:
+    same bytes and flag words, nothing lost, every packet placed."""
+    rng, packed, flags, pk = _assembly_case(60)
+    for order in (np.arange(len(pk)), rng.permutation(len(pk))):
+        got = orc.assemble(pk[order], 37, 3, 5, 1000, 64)
+        assert np.array_equal(got[0], packed)
+        assert np.array_equal(got[2], flags)
+        assert not got[1].any()
+        assert list(got[3]) == [len(pk), 0, 0, 0, len(pk), 0]
+
+
+def pin_assemble_faults(orc):
+    """Drops, duplicates with different payloads, reordering, packets from
+    outside the window, of unknown streams and with a wrong input count:
+    the first arrival of each (stream, slot) is placed, empty places read
+    0 + 0i with no flags and a lost block, against a direct reconstruction."""
+    for seed, N in ((61, 37), (62, 64)):
+        rng, packed, flags, pk = _assembly_case(seed, N=N)
+        pk = synth.network_faults(rng, pk, p_drop=0.15, p_dup=0.2, window=6, n_stray=3)
+        bad = pk[:2].copy()
+        h = bad[0, :16].view("<u8").copy()
+        h[1] = np.uint64(99) | (np.uint64(N) << np.uint64(32))      # unknown stream
+        bad[0, :16] = h.view(np.uint8)
+        h = bad[1, :16].view("<u8").copy()
+        h[1] = (h[1] & np.uint64(0xffffffff)) | (np.uint64(N + 1) << np.uint64(32))
+        bad[1, :16] = h.view(np.uint8)                               # wrong input count
+        early = pk[:1].copy()
+        h = early[0, :16].view("<u8").copy()
+        h[0] = np.uint64(999)                                        # before the window
+        early[0, :16] = h.view(np.uint8)
+        pk = np.concatenate([pk[:5], bad, early, pk[5:]])
+        got = orc.assemble(pk, N, 3, 5, 1000, 64)
+        want = _brute_assemble(pk, N, 3, 5, 1000, 64)
+        for g, w in zip(got, want):
+            assert np.array_equal(g, w), seed
+        st = got[3]
+        assert st[1] >= 4 and st[2] >= 1 and st[3] >= 1 and st[5] > 0 and st[0] > st[4]
+
+
 PINS = [
     pin_decode_roundtrip,
     pin_tri_index,
@@ -459,4 +549,6 @@ PINS = [
     pin_flag_counts_brute_force,
     pin_flagged_correlation,
     pin_flag_normalize,
+    pin_assemble_roundtrip,
+    pin_assemble_faults,
 ]

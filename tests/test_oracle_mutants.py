@@ -49,12 +49,24 @@ MUTANTS = [
      "if (word != 0)\n                    continue;", 1),
     ("flag_norm_intersection_sign", "+ d[p];", "- d[p];", 1),
     ("flag_norm_one_counter", " - c[(int64_t)f * N + j] + d[p];", " + d[p];", 1),
-    ("flag_zero_byte", "= 0x88;", "= 0x00;", 1),
+    ("flag_zero_byte", "packed[((int64_t)t * F + f) * N + i] = 0x88;",
+     "packed[((int64_t)t * F + f) * N + i] = 0x00;", 1),
     ("flagged_one_side", "(input_flagged(flags, N, T, f, t, i) ||\n", "(0 ||\n", 1),
     ("flag_word_bit", "i / 32] >> (i % 32))", "i / 32] >> (31 - i % 32))", 1),
     ("normalize_pairs_float",
      "(float)((double)vis[2 * q + k] / (double)m)", "(float)vis[2 * q + k] / (float)m", 1),
     ("normalize_pairs_zero", "m == 0 ? 0.0f : ", "", 1),
+    # frame assembly (Sec. II-A)
+    ("assemble_last_wins", "if (filled[s * slots + k])\n            continue;",
+     "if (0)\n            continue;", 1),
+    ("assemble_zero_byte", "packed[(t * F + f) * N + i] = 0x88;", "packed[(t * F + f) * N + i] = 0;", 1),
+    ("assemble_mask_not_set", "mask[f * slots + k] = (uint8_t)lost;", "mask[f * slots + k] = 0;", 1),
+    ("assemble_band_order", "int64_t t = k * S + smp, f = s * NB + b;",
+     "int64_t t = k * S + smp, f = s * NB + (NB - 1 - b);", 1),
+    ("assemble_footer_order", "(((int64_t)smp * NB + b) * W) * 4;", "(((int64_t)b * S + smp) * W) * 4;", 1),
+    ("assemble_window_start", "if (seq < (uint64_t)seq0 ||", "if (seq <= (uint64_t)seq0 ||", 1),
+    ("assemble_stream_base", "int64_t s = (int64_t)sid - stream_base;", "int64_t s = (int64_t)sid;", 1),
+    ("assemble_lost_flags_kept", "flags[(f * T + t) * W + w] = 0;", ";", 1),
 ]
 
 
