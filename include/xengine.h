@@ -161,6 +161,37 @@ xe_status xe_normalize_flagged(xe_handle h, const int32_t *vis,
                                int32_t N, int32_t F, float *out,
                                int32_t *n_out, void *stream);
 
+/* Frame assembly from F-engine UDP packets (Sec. II-A: the network thread
+ * places each packet's data by its sequence number, writes zeros where a
+ * packet is missing, puts out-of-order packets in their own place and
+ * ignores duplicates).  Packet layout, XE_PACKET_BYTES(N) bytes: a 16-byte
+ * header (uint64 sequence number, uint32 stream id, uint32 input count N,
+ * little-endian), the data of 4 samples x 8 bands x N inputs (one byte
+ * each, in that order), then the flag bit-fields of the 4 x 8 (sample,
+ * band) pairs, ceil(N/32) uint32 words each (bit i % 32 of word i / 32 =
+ * input i, as for xe_flag_accumulate).  Stream stream_base + s carries
+ * channels 8 s .. 8 s + 7 of the frame; the packet with sequence number
+ * seq0 + k holds samples 4 k .. 4 k + 3. */
+#define XE_PACKET_BYTES(N) (16 + 32 * (int64_t)(N) + 128 * (((int64_t)(N) + 31) / 32))
+
+/* Build one frame from n_packets packets (device memory, arrival order,
+ * XE_PACKET_BYTES(N) apart, 4-byte aligned): packed [T][8 n_streams][N],
+ * loss_mask [8 n_streams][T/4] (block = one packet, B = 4), flags
+ * [8 n_streams][T][ceil(N/32)] (may be NULL: not written).  For each
+ * (stream, slot) the packet that arrived first (lowest index) is placed;
+ * where none arrived the data is 0x88 (0 + 0i), the flags 0 and the block
+ * lost.  Every output element is written.  stats (device, int64[6]):
+ * packets inside the window, outside it (sequence number), of an unknown
+ * stream, with another input count, places filled, places left empty;
+ * duplicates = stats[0] - stats[4].  T a multiple of 4; the handle's
+ * workspace holds 4 bytes per (stream, slot); n_packets < 2^31 - 1.
+ * Capture-safe (kernels only). */
+xe_status xe_assemble_frame(xe_handle h, const uint8_t *packets,
+                            int64_t n_packets, int32_t N, int32_t n_streams,
+                            int32_t stream_base, int64_t seq0, int32_t T,
+                            uint8_t *packed, uint8_t *loss_mask,
+                            uint32_t *flags, int64_t *stats, void *stream);
+
 /* One correlator instance of a batch: a frame of one sub-array with its own
  * N, F, T and B, accumulated into its own vis and count.  Pointers are
  * device pointers; the array of instances itself is host memory. */

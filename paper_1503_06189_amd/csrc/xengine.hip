@@ -15,6 +15,7 @@
 #include "plan.hpp"
 #include "xcorr_kernels.hpp"
 #include "flag_kernels.hpp"
+#include "assemble_kernels.hpp"
 
 // Batch plans live in a device area allocated with the handle: kRingSlots
 // slots that xe_accumulate_batch cycles through (each guarded by an event,
@@ -674,6 +675,62 @@ xe_status xe_normalize_flagged(xe_handle h, const int32_t *vis, const int64_t *c
                        (hipStream_t)stream, vis, count, dcount, out, n_out, N, F);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "normalize flagged launch");
+    return XE_OK;
+}
+
+xe_status xe_assemble_frame(xe_handle h, const uint8_t *packets, int64_t n_packets, int32_t N,
+                            int32_t n_streams, int32_t stream_base, int64_t seq0, int32_t T,
+                            uint8_t *packed, uint8_t *loss_mask, uint32_t *flags, int64_t *stats,
+                            void *stream) {
+    using namespace xe::pkt;
+    if (!h) return XE_ERR_ARG;
+    if (n_streams < 1) return fail(h, XE_ERR_ARG, "n_streams must be >= 1");
+    if (T % kSamples != 0) return fail(h, XE_ERR_ARG, "T must be a multiple of 4");
+    if (n_packets < 0 || n_packets >= (int64_t)kNone) return fail(h, XE_ERR_ARG, "bad n_packets");
+    if ((int64_t)kBands * n_streams > INT32_MAX) return fail(h, XE_ERR_ARG, "n_streams too large");
+    xe_status s = check_shape(h, N, kBands * n_streams, T, kSamples);
+    if (s != XE_OK) return s;
+    if ((n_packets > 0 && !packets) || !packed || !loss_mask || !stats)
+        return fail(h, XE_ERR_ARG, "null pointer");
+    if (!aligned(packets, 4) || !aligned(flags, 4) || !aligned(stats, 8))
+        return fail(h, XE_ERR_ALIGN, "packets/flags not 4-byte or stats not 8-byte aligned");
+    const int64_t slots = T / kSamples;
+    if ((size_t)(n_streams * slots) * 4 > h->workspace_bytes && h->device != XE_DEVICE_NONE)
+        return fail(h, XE_ERR_WORKSPACE, "owner table does not fit the workspace");
+    if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
+    Args a{};
+    a.packets = packets;
+    a.n_packets = n_packets;
+    a.pbytes = XE_PACKET_BYTES(N);
+    a.N = N;
+    a.W = (N + 31) / 32;
+    a.n_streams = n_streams;
+    a.stream_base = stream_base;
+    a.seq0 = seq0;
+    a.T = T;
+    a.slots = (int)slots;
+    a.packed = packed;
+    a.mask = loss_mask;
+    a.flags = flags;
+    a.owner = (int32_t *)h->workspace;
+    a.stats = (unsigned long long *)stats;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t places = (int64_t)n_streams * slots;
+    hipLaunchKernelGGL(reset_kernel, dim3((unsigned)std::min<int64_t>((places + 255) / 256, 4096)),
+                       dim3(256), 0, st, a.owner, places, a.stats);
+    if (n_packets > 0)
+        hipLaunchKernelGGL(claim_kernel, dim3((unsigned)((n_packets + 255) / 256)), dim3(256), 0,
+                           st, a);
+    if (N % 2 == 0 && aligned(packed, 16) && aligned(packets, 16))
+        hipLaunchKernelGGL(place_kernel<true>, dim3((unsigned)places), dim3(kPlaceThreads), 0, st,
+                           a);
+    else
+        hipLaunchKernelGGL(place_kernel<false>, dim3((unsigned)places), dim3(kPlaceThreads), 0,
+                           st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "assemble launch");
     return XE_OK;
 }
 

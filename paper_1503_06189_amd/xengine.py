@@ -34,7 +34,8 @@ EXPORTS = ("xe_create", "xe_destroy", "xe_status_string", "xe_last_error",
            "xe_correlate_frame", "xe_accumulate", "xe_normalize",
            "xe_accumulate_batch", "xe_batch_plan", "xe_batch_run", "xe_batch_release",
            "xe_batch_query", "xe_plan_query",
-           "xe_flag_accumulate", "xe_apply_flags", "xe_normalize_flagged")
+           "xe_flag_accumulate", "xe_apply_flags", "xe_normalize_flagged",
+           "xe_assemble_frame")
 
 
 class XEngineUnavailable(RuntimeError):
@@ -103,6 +104,9 @@ def lib() -> ctypes.CDLL:
             L.xe_apply_flags.argtypes = [vp, vp, vp, i32, i32, i32, vp]
             L.xe_normalize_flagged.restype = i32
             L.xe_normalize_flagged.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
+            L.xe_assemble_frame.restype = i32
+            L.xe_assemble_frame.argtypes = [vp, vp, ctypes.c_int64, i32, i32, i32,
+                                            ctypes.c_int64, i32, vp, vp, vp, vp, vp]
             L.xe_accumulate_batch.restype = i32
             L.xe_accumulate_batch.argtypes = [vp, ctypes.POINTER(Instance), i32, vp]
             L.xe_batch_plan.restype = i32
@@ -352,6 +356,53 @@ def normalize_flagged(vis, count, dcount, out=None, n_out=None,
         ctypes.c_void_p(n_out.data_ptr() if n_out is not None else None),
         _stream_ptr(stream)))
     return out
+
+
+# -- frame assembly from packets (Sec. II-A) ---------------------------------
+
+def packet_bytes(N: int) -> int:
+    """XE_PACKET_BYTES(N): header + [4][8][N] data + [4][8][ceil(N/32)] flag words."""
+    return 16 + 32 * N + 128 * ((N + 31) // 32)
+
+
+def assemble_frame(packets, N: int, n_streams: int, stream_base: int, seq0: int, T: int,
+                   packed=None, mask=None, flags=None, stats=None, with_flags: bool = True,
+                   handle: Optional[Handle] = None, stream=None):
+    """Frame, loss mask (B = 4), flags and counters from a CUDA uint8 tensor
+    of packets [n, packet_bytes(N)] in arrival order."""
+    import torch
+    pb = packet_bytes(N)
+    if packets.dtype != torch.uint8 or packets.dim() != 2 or not packets.is_cuda or \
+            not packets.is_contiguous() or (packets.shape[0] and packets.shape[1] != pb):
+        raise ValueError(f"packets must be a contiguous CUDA uint8 tensor [n, {pb}]")
+    dev = packets.device
+    F, W = 8 * n_streams, (N + 31) // 32
+    if packed is None:
+        packed = torch.empty((T, F, N), dtype=torch.uint8, device=dev)
+    if mask is None:
+        mask = torch.empty((F, T // 4), dtype=torch.uint8, device=dev)
+    if flags is None and with_flags:
+        flags = torch.empty((F, T, W), dtype=torch.int32, device=dev)
+    if stats is None:
+        stats = torch.empty(6, dtype=torch.int64, device=dev)
+    if tuple(packed.shape) != (T, F, N) or packed.dtype != torch.uint8 or \
+            not packed.is_contiguous():
+        raise ValueError(f"packed must be contiguous uint8 [{T}, {F}, {N}]")
+    if tuple(mask.shape) != (F, T // 4) or mask.dtype != torch.uint8 or not mask.is_contiguous():
+        raise ValueError(f"mask must be contiguous uint8 [{F}, {T // 4}]")
+    if flags is not None and (tuple(flags.shape) != (F, T, W) or flags.dtype != torch.int32
+                              or not flags.is_contiguous()):
+        raise ValueError(f"flags must be contiguous int32 [{F}, {T}, {W}]")
+    if stats.dtype != torch.int64 or stats.numel() != 6 or not stats.is_contiguous():
+        raise ValueError("stats must be contiguous int64 [6]")
+    h = handle or default_handle(dev.index)
+    h.check(lib().xe_assemble_frame(
+        h.ptr, ctypes.c_void_p(packets.data_ptr()), int(packets.shape[0]), N, n_streams,
+        stream_base, seq0, T, ctypes.c_void_p(packed.data_ptr()),
+        ctypes.c_void_p(mask.data_ptr()),
+        ctypes.c_void_p(flags.data_ptr() if flags is not None else None),
+        ctypes.c_void_p(stats.data_ptr()), _stream_ptr(stream)))
+    return packed, mask, flags, stats
 
 
 def _instances(items: Sequence[Tuple]):

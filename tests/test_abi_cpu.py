@@ -261,3 +261,22 @@ def test_flag_checks(L, h):
     assert nrm(vis=0x100004) == xe.XE_ERR_ALIGN
     assert nrm(d=0x300002) == xe.XE_ERR_ALIGN
     assert nrm(n_out=0x500002) == xe.XE_ERR_ALIGN
+
+
+def test_assemble_checks(L, h):
+    def asm(packets=0x100000, n=10, N=40, S=2, base=0, seq0=0, T=64, packed=0x200000,
+            mask=0x300000, flags=0x400000, stats=0x500000, hh=h):
+        return L.xe_assemble_frame(hh, ctypes.c_void_p(packets), n, N, S, base, seq0, T,
+                                   ctypes.c_void_p(packed), ctypes.c_void_p(mask),
+                                   ctypes.c_void_p(flags), ctypes.c_void_p(stats), None)
+    assert asm() == xe.XE_ERR_NO_DEVICE
+    assert asm(flags=0) == xe.XE_ERR_NO_DEVICE          # flags are optional
+    assert asm(n=0, packets=0) == xe.XE_ERR_NO_DEVICE   # an empty batch: every place lost
+    assert asm(hh=None) == xe.XE_ERR_ARG
+    for bad in (dict(packets=0), dict(packed=0), dict(mask=0), dict(stats=0), dict(N=0),
+                dict(S=0), dict(T=62), dict(T=0), dict(n=-1)):
+        assert asm(**bad) == xe.XE_ERR_ARG, bad
+    assert asm(packets=0x100002) == xe.XE_ERR_ALIGN
+    assert asm(stats=0x500004) == xe.XE_ERR_ALIGN
+    assert xe.packet_bytes(256) == 16 + 8192 + 1024
+    assert xe.packet_bytes(37) == 16 + 32 * 37 + 128 * 2
