@@ -24,6 +24,8 @@ Prints ONE JSON line.  Fields beyond the common ones:
                 (bursty 0.1% flags, and 50% as a stress case) against HBM,
                 the zeroing and per-baseline normalisation kernels, and the
                 flagged step against the plain one
+  assembly      the same frame assembled on the GPU from 32768 F-engine
+                packets (1% dropped, 0.5% duplicated, reordered) against HBM
   serving       8 streams of 4096-sample frames offered with Poisson
                 arrivals at 51.2 Gb/s in total from pinned host memory:
                 p50/p99 frame latency (arrival to accumulated); plus the
@@ -257,6 +259,64 @@ def flags_leg(torch, reps: int):
     }
 
 
+def assembly_leg(torch, reps: int):
+    """Frame assembly from F-engine packets (xe_assemble_frame) for the
+    pathfinder share: 8 links x 8 bands, 16384 samples, 32768 packets of
+    9232 B with 1% dropped, 0.5% duplicated and reordering, the packets
+    already in device memory.  HBM roofline: packets read once, frame, flags
+    and mask written once."""
+    import numpy as np
+    from paper_1503_06189_amd import synth, xengine
+    dev = torch.device("cuda:0")
+    h = xengine.default_handle(0)
+    stream = torch.cuda.current_stream()
+    fr = synth.pathfinder(p_loss=0.0)
+    rng = np.random.default_rng(77)
+    flags = synth.fengine_flags(rng, fr.T, fr.F, fr.N, 1e-3)
+    pk = synth.packetize(fr.packed, flags, stream_base=0, seq0=0)
+    pk = synth.network_faults(rng, pk, p_drop=0.01, p_dup=0.005, window=64)
+    dpk = torch.from_numpy(pk).to(dev)
+    S = fr.F // 8
+    out = xengine.assemble_frame(dpk, fr.N, S, 0, 0, fr.T, handle=h, stream=stream)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        xengine.assemble_frame(dpk, fr.N, S, 0, 0, fr.T, *out, handle=h, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, 2)
+    e0.record(stream)
+    for _ in range(reps):
+        xengine.assemble_frame(dpk, fr.N, S, 0, 0, fr.T, *out, handle=h, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    # the copy of the receive ring from pinned host memory, for context
+    host = torch.from_numpy(pk).pin_memory()
+    dpk.copy_(host, non_blocking=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(3):
+        dpk.copy_(host, non_blocking=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    h2d_ms = e0.elapsed_time(e1) / 3
+    st = out[3].cpu().tolist()
+    W = synth.flag_words(fr.N)
+    alg = pk.nbytes + fr.T * fr.F * fr.N + fr.F * fr.T * W * 4 + fr.F * fr.T // 4
+    gbps = alg / (ms / 1e3) / 1e9
+    return {
+        "workload": f"{fr.name} from {len(pk)} packets of {pk.shape[1]} B, "
+                    "1% dropped, 0.5% duplicated, reordered",
+        "assemble_us": round(ms * 1e3, 2),
+        "packets_per_s": round(len(pk) / (ms / 1e3), 0),
+        "placed": st[4], "lost": st[5], "duplicates": st[0] - st[4],
+        "h2d_packets_us": round(h2d_ms * 1e3, 1),
+        "h2d_gbps": round(pk.nbytes / (h2d_ms / 1e3) / 1e9, 1),
+        "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                     "alg_bytes": int(alg)},
+    }
+
+
 def serving_leg(torch, seconds: float):
     from paper_1503_06189_amd import serve, synth
     specs = synth.streaming_streams()
@@ -293,6 +353,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-flags", action="store_true")
+    ap.add_argument("--no-assembly", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 256 MiB once (a kernel of known "
@@ -400,6 +461,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_flags:
         res["flags"] = flags_leg(torch, reps=max(5, min(50, args.steps)))
+        torch.cuda.empty_cache()
+    if not args.no_assembly:
+        res["assembly"] = assembly_leg(torch, reps=max(5, min(50, args.steps)))
         torch.cuda.empty_cache()
     if not args.no_serving:
         res["serving"] = serving_leg(torch, args.serve_seconds)

@@ -729,6 +729,8 @@ xe_status xe_assemble_frame(xe_handle h, const uint8_t *packets, int64_t n_packe
     else
         hipLaunchKernelGGL(place_kernel<false>, dim3((unsigned)places), dim3(kPlaceThreads), 0,
                            st, a);
+    hipLaunchKernelGGL(count_kernel, dim3((unsigned)std::min<int64_t>((places + 255) / 256, 256)),
+                       dim3(256), 0, st, a.owner, places, a.stats);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "assemble launch");
     return XE_OK;
