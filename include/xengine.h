@@ -192,6 +192,24 @@ xe_status xe_assemble_frame(xe_handle h, const uint8_t *packets,
                             uint8_t *packed, uint8_t *loss_mask,
                             uint32_t *flags, int64_t *stats, void *stream);
 
+/* Per-input time shifting (the caption of Fig. 4, Sec. II-B, lists time
+ * shifting among the extra operations of the GPU kernel stage and gives no
+ * algorithm; this is an integer delay per input).  For every channel,
+ *     packed_out[t][f][i] = packed_in[t - delays[i]][f][i]
+ * when 0 <= t - delays[i] < T; otherwise 0x88 (0 + 0i).  flags_out
+ * ([F][T][ceil(N/32)], may be NULL) receives the F-engine flags moved with
+ * their data (flags_in, same layout, may be NULL = none), with the bit of
+ * every sample shifted in from outside the frame set, so that
+ * xe_flag_accumulate / xe_normalize_flagged count those samples out.
+ * delays: device int32 [N], any values.  A channel's loss mask cannot
+ * follow per-input delays: shift frames whose lost samples are already
+ * flagged in flags_in, and pass no loss mask for the shifted frame.  The
+ * outputs may not overlap the inputs.  Capture-safe (kernels only). */
+xe_status xe_time_shift(xe_handle h, const uint8_t *packed_in,
+                        const uint32_t *flags_in, const int32_t *delays,
+                        int32_t N, int32_t F, int32_t T, uint8_t *packed_out,
+                        uint32_t *flags_out, void *stream);
+
 /* One correlator instance of a batch: a frame of one sub-array with its own
  * N, F, T and B, accumulated into its own vis and count.  Pointers are
  * device pointers; the array of instances itself is host memory. */

@@ -80,6 +80,8 @@ class Oracle:
                                                  _p, _p]
         lib.oracle_normalize_pairs.restype = None
         lib.oracle_normalize_pairs.argtypes = [_p, _p, _i32, _i32, _p]
+        lib.oracle_time_shift.restype = None
+        lib.oracle_time_shift.argtypes = [_p, _p, _p, _i32, _i32, _i32, _p, _p]
         lib.oracle_assemble.restype = None
         lib.oracle_assemble.argtypes = [_p, _i64, _i32, _i32, _i32, _i64, _i32, _p, _p, _p, _p]
 
@@ -255,6 +257,22 @@ class Oracle:
         self._lib.oracle_assemble(_ptr(packets), packets.shape[0], N, n_streams, stream_base,
                                   seq0, T, _ptr(packed), _ptr(mask), _ptr(flags), _ptr(stats))
         return packed, mask, flags, stats
+
+    # -- per-input time shifting ------------------------------------------------
+    def time_shift(self, packed, flags, delays):
+        """(out [T][F][N], flags_out [F][T][W]): input i delayed by delays[i]."""
+        packed = np.ascontiguousarray(packed, dtype=np.uint8)
+        T, F, N = packed.shape
+        if flags is not None:
+            flags = self._flag_args(flags, T, F, N)
+        delays = np.ascontiguousarray(delays, dtype=np.int32)
+        if delays.shape != (N,):
+            raise ValueError("delays must be int32 [N]")
+        out = np.full_like(packed, 0x5A)
+        fo = np.full((F, T, (N + 31) // 32), 0xDEADBEEF, dtype=np.uint32)
+        self._lib.oracle_time_shift(_ptr(packed), _ptr(flags), _ptr(delays), N, F, T,
+                                    _ptr(out), _ptr(fo))
+        return out, fo
 
 
 _cached: Optional[Oracle] = None

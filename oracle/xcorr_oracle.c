@@ -425,3 +425,38 @@ void oracle_assemble(const uint8_t *packets, int64_t n_packets, int32_t N,
         }
     free(filled);
 }
+
+/* ---------------------------------------------------------------------
+ * Per-input time shifting (the caption of Fig. 4, Sec. II-B, names time
+ * shifting among the extra operations of the GPU kernel stage and gives no
+ * algorithm; the reading here is an integer sample delay per input).  Input i of every channel is delayed
+ * by delays[i] samples: out[t][f][i] = in[t - d_i][f][i] when 0 <= t - d_i
+ * < T.  A sample shifted in from outside the frame has no data: it becomes
+ * 0x88 (0 + 0i) and a flagged point, so the per-baseline normalisation
+ * counts it out.  F-engine flags move with their data: flags_out[f][t] of
+ * input i = flags_in[f][t - d_i] of input i (flags_in may be NULL = none),
+ * or 1 outside the frame.  Bits past input N-1 are written as 0.
+ * --------------------------------------------------------------------- */
+void oracle_time_shift(const uint8_t *packed, const uint32_t *flags_in,
+                       const int32_t *delays, int32_t N, int32_t F, int32_t T,
+                       uint8_t *out, uint32_t *flags_out)
+{
+    int64_t W = ((int64_t)N + 31) / 32;
+    for (int64_t f = 0; f < F; ++f)
+        for (int64_t t = 0; t < T; ++t)
+            for (int64_t w = 0; w < W; ++w)
+                flags_out[(f * T + t) * W + w] = 0;
+    for (int64_t t = 0; t < T; ++t)
+        for (int64_t f = 0; f < F; ++f)
+            for (int i = 0; i < N; ++i) {
+                int64_t src = t - delays[i];
+                int inside = src >= 0 && src < T;
+                out[(t * F + f) * N + i] = inside ? packed[(src * F + f) * N + i] : 0x88;
+                int flagged = 1;
+                if (inside)
+                    flagged = flags_in != NULL &&
+                              input_flagged(flags_in, N, T, (int)f, (int)src, i);
+                if (flagged)
+                    flags_out[(f * T + t) * W + i / 32] |= 1u << (i % 32);
+            }
+}

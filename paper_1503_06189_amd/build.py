@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxengine.so")
 SOURCES = [os.path.join(CSRC, "xengine.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("plan.hpp", "xcorr_kernels.hpp", "flag_kernels.hpp", "assemble_kernels.hpp")] + \
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("plan.hpp", "xcorr_kernels.hpp", "flag_kernels.hpp", "assemble_kernels.hpp", "shift_kernels.hpp")] + \
     [os.path.join(ROOT, "include", "xengine.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

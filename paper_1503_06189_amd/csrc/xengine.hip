@@ -16,6 +16,7 @@
 #include "xcorr_kernels.hpp"
 #include "flag_kernels.hpp"
 #include "assemble_kernels.hpp"
+#include "shift_kernels.hpp"
 
 // Batch plans live in a device area allocated with the handle: kRingSlots
 // slots that xe_accumulate_batch cycles through (each guarded by an event,
@@ -733,6 +734,51 @@ xe_status xe_assemble_frame(xe_handle h, const uint8_t *packets, int64_t n_packe
                        dim3(256), 0, st, a.owner, places, a.stats);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "assemble launch");
+    return XE_OK;
+}
+
+xe_status xe_time_shift(xe_handle h, const uint8_t *packed_in, const uint32_t *flags_in,
+                        const int32_t *delays, int32_t N, int32_t F, int32_t T,
+                        uint8_t *packed_out, uint32_t *flags_out, void *stream) {
+    if (!h) return XE_ERR_ARG;
+    xe_status s = check_shape(h, N, F, T, 1);
+    if (s != XE_OK) return s;
+    if (!packed_in || !delays || !packed_out) return fail(h, XE_ERR_ARG, "null pointer");
+    if (!aligned(delays, 4) || !aligned(flags_in, 4) || !aligned(flags_out, 4))
+        return fail(h, XE_ERR_ALIGN, "delays/flags not 4-byte aligned");
+    const int W = (N + 31) / 32;
+    const int64_t fbytes = (int64_t)F * T * W * 4, pbytes = (int64_t)T * F * N;
+    auto overlap = [](const void *a, int64_t na, const void *b, int64_t nb) {
+        const char *x = (const char *)a, *y = (const char *)b;
+        return a && b && x < y + nb && y < x + na;
+    };
+    if (overlap(packed_out, pbytes, packed_in, pbytes) ||
+        overlap(flags_out, fbytes, flags_in, fbytes) ||
+        overlap(flags_out, fbytes, packed_in, pbytes) ||
+        overlap(packed_out, pbytes, flags_in, fbytes) ||
+        overlap(packed_out, pbytes, flags_out, fbytes))
+        return fail(h, XE_ERR_ARG, "outputs overlap inputs or each other");
+    if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    const bool vec = N % 4 == 0 && aligned(packed_in, 4) && aligned(packed_out, 4);
+    const int64_t items = (int64_t)T * F * (vec ? N / 4 : N);
+    const unsigned blocks = (unsigned)std::min<int64_t>((items + 255) / 256, 65536);
+    if (vec)
+        hipLaunchKernelGGL(xe::shift::data_kernel<true>, dim3(blocks), dim3(256), 0, st,
+                           packed_in, delays, packed_out, N, F, T);
+    else
+        hipLaunchKernelGGL(xe::shift::data_kernel<false>, dim3(blocks), dim3(256), 0, st,
+                           packed_in, delays, packed_out, N, F, T);
+    if (flags_out) {
+        const int64_t words = (int64_t)F * T * W;
+        hipLaunchKernelGGL(xe::shift::flag_kernel,
+                           dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)),
+                           dim3(256), 0, st, flags_in, delays, flags_out, N, F, T, W);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "time shift launch");
     return XE_OK;
 }
 

@@ -35,7 +35,7 @@ EXPORTS = ("xe_create", "xe_destroy", "xe_status_string", "xe_last_error",
            "xe_accumulate_batch", "xe_batch_plan", "xe_batch_run", "xe_batch_release",
            "xe_batch_query", "xe_plan_query",
            "xe_flag_accumulate", "xe_apply_flags", "xe_normalize_flagged",
-           "xe_assemble_frame")
+           "xe_assemble_frame", "xe_time_shift")
 
 
 class XEngineUnavailable(RuntimeError):
@@ -104,6 +104,8 @@ def lib() -> ctypes.CDLL:
             L.xe_apply_flags.argtypes = [vp, vp, vp, i32, i32, i32, vp]
             L.xe_normalize_flagged.restype = i32
             L.xe_normalize_flagged.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
+            L.xe_time_shift.restype = i32
+            L.xe_time_shift.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp, vp, vp]
             L.xe_assemble_frame.restype = i32
             L.xe_assemble_frame.argtypes = [vp, vp, ctypes.c_int64, i32, i32, i32,
                                             ctypes.c_int64, i32, vp, vp, vp, vp, vp]
@@ -403,6 +405,36 @@ def assemble_frame(packets, N: int, n_streams: int, stream_base: int, seq0: int,
         ctypes.c_void_p(flags.data_ptr() if flags is not None else None),
         ctypes.c_void_p(stats.data_ptr()), _stream_ptr(stream)))
     return packed, mask, flags, stats
+
+
+# -- per-input time shifting ---------------------------------------------------
+
+def time_shift(packed, delays, flags=None, out=None, flags_out=None, with_flags: bool = True,
+               handle: Optional[Handle] = None, stream=None):
+    """Input i delayed by delays[i] samples (CUDA int32 [N]); samples
+    shifted in from outside the frame are 0 + 0i and flagged in flags_out."""
+    import torch
+    T, F, N = _check_frame(packed, None, 1)
+    W = (N + 31) // 32
+    if delays.dtype != torch.int32 or tuple(delays.shape) != (N,) or not delays.is_cuda or \
+            not delays.is_contiguous():
+        raise ValueError(f"delays must be a contiguous CUDA int32 tensor [{N}]")
+    if flags is not None:
+        _check_flags(flags, F, T, N)
+    if out is None:
+        out = torch.empty_like(packed)
+    if flags_out is None and with_flags:
+        flags_out = torch.empty((F, T, W), dtype=torch.int32, device=packed.device)
+    if flags_out is not None:
+        _check_flags(flags_out, F, T, N)
+    h = handle or default_handle(packed.device.index)
+    h.check(lib().xe_time_shift(
+        h.ptr, ctypes.c_void_p(packed.data_ptr()),
+        ctypes.c_void_p(flags.data_ptr() if flags is not None else None),
+        ctypes.c_void_p(delays.data_ptr()), N, F, T, ctypes.c_void_p(out.data_ptr()),
+        ctypes.c_void_p(flags_out.data_ptr() if flags_out is not None else None),
+        _stream_ptr(stream)))
+    return out, flags_out
 
 
 def _instances(items: Sequence[Tuple]):

@@ -532,6 +532,43 @@ def pin_assemble_faults(orc):
         assert st[1] >= 4 and st[2] >= 1 and st[3] >= 1 and st[5] > 0 and st[0] > st[4]
 
 
+# ---------------------------------------------------------------------------
+# per-input time shifting
+# ---------------------------------------------------------------------------
+
+def pin_time_shift(orc):
+    """Zero delays copy the frame and its flags; each input's column equals
+    numpy's shifted slice with 0x88 and a flag where the source lies
+    outside; one common delay d leaves V over the frame equal to V of the
+    first T - d samples of the original (same pairs, fewer samples)."""
+    rng = np.random.default_rng(70)
+    T, F, N = 40, 3, 37
+    packed = rng.integers(0, 256, (T, F, N), dtype=np.uint8)
+    flags = synth.random_flags(rng, T, F, N, 0.2, garbage_padding=True)
+    bits = synth.unpack_flags(flags, N)
+    out, fo = orc.time_shift(packed, flags, np.zeros(N, np.int32))
+    assert np.array_equal(out, packed)
+    assert np.array_equal(synth.unpack_flags(fo, N), bits)
+    assert np.array_equal(fo, synth.pack_flags(bits))           # padding bits cleared
+    d = rng.integers(-6, 7, N).astype(np.int32)
+    d[0], d[1] = T + 3, -T
+    out, fo = orc.time_shift(packed, flags, d)
+    ob = synth.unpack_flags(fo, N)
+    for i in range(N):
+        for t in range(T):
+            src = t - d[i]
+            if 0 <= src < T:
+                assert (out[t, :, i] == packed[src, :, i]).all()
+                assert (ob[t, :, i] == bits[src, :, i]).all()
+            else:
+                assert (out[t, :, i] == synth.ZERO_BYTE).all() and ob[t, :, i].all()
+    out, fo = orc.time_shift(packed, None, np.full(N, 5, np.int32))
+    vs, _ = orc.correlate(out)
+    vo, _ = orc.correlate(packed[:T - 5])
+    assert np.array_equal(vs, vo)
+    assert synth.unpack_flags(fo, N)[:5].all() and not synth.unpack_flags(fo, N)[5:].any()
+
+
 PINS = [
     pin_decode_roundtrip,
     pin_tri_index,
@@ -551,4 +588,5 @@ PINS = [
     pin_flag_normalize,
     pin_assemble_roundtrip,
     pin_assemble_faults,
+    pin_time_shift,
 ]

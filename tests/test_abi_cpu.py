@@ -280,3 +280,20 @@ def test_assemble_checks(L, h):
     assert asm(stats=0x500004) == xe.XE_ERR_ALIGN
     assert xe.packet_bytes(256) == 16 + 8192 + 1024
     assert xe.packet_bytes(37) == 16 + 32 * 37 + 128 * 2
+
+
+def test_time_shift_checks(L, h):
+    def sh(pin=0x100000, fin=0x200000, d=0x300000, N=40, F=2, T=64, pout=0x400000,
+           fout=0x500000, hh=h):
+        return L.xe_time_shift(hh, ctypes.c_void_p(pin), ctypes.c_void_p(fin),
+                               ctypes.c_void_p(d), N, F, T, ctypes.c_void_p(pout),
+                               ctypes.c_void_p(fout), None)
+    assert sh() == xe.XE_ERR_NO_DEVICE
+    assert sh(fin=0, fout=0) == xe.XE_ERR_NO_DEVICE     # flags optional
+    assert sh(hh=None) == xe.XE_ERR_ARG
+    for bad in (dict(pin=0), dict(d=0), dict(pout=0), dict(N=0), dict(T=0)):
+        assert sh(**bad) == xe.XE_ERR_ARG, bad
+    assert sh(pout=0x100000 + 16) == xe.XE_ERR_ARG       # overlaps the input frame
+    assert sh(fout=0x200000 + 4) == xe.XE_ERR_ARG        # overlaps the input flags
+    assert sh(d=0x300002) == xe.XE_ERR_ALIGN
+    assert sh(fout=0x500002) == xe.XE_ERR_ALIGN

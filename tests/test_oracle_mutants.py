@@ -67,6 +67,12 @@ MUTANTS = [
     ("assemble_window_start", "if (seq < (uint64_t)seq0 ||", "if (seq <= (uint64_t)seq0 ||", 1),
     ("assemble_stream_base", "int64_t s = (int64_t)sid - stream_base;", "int64_t s = (int64_t)sid;", 1),
     ("assemble_lost_flags_kept", "flags[(f * T + t) * W + w] = 0;", ";", 1),
+    # per-input time shifting
+    ("shift_sign", "int64_t src = t - delays[i];", "int64_t src = t + delays[i];", 1),
+    ("shift_edge_not_flagged", "int flagged = 1;", "int flagged = 0;", 1),
+    ("shift_flags_not_moved", "input_flagged(flags_in, N, T, (int)f, (int)src, i);",
+     "input_flagged(flags_in, N, T, (int)f, (int)t, i);", 1),
+    ("shift_edge_byte", ": 0x88;", ": 0x00;", 1),
 ]
 
 
