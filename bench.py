@@ -26,6 +26,8 @@ Prints ONE JSON line.  Fields beyond the common ones:
                 flagged step against the plain one
   assembly      the same frame assembled on the GPU from 32768 F-engine
                 packets (1% dropped, 0.5% duplicated, reordered) against HBM
+  shift         per-input time shifting of the same frame and its flags
+                against HBM
   serving       8 streams of 4096-sample frames offered with Poisson
                 arrivals at 51.2 Gb/s in total from pinned host memory:
                 p50/p99 frame latency (arrival to accumulated); plus the
@@ -317,6 +319,43 @@ def assembly_leg(torch, reps: int):
     }
 
 
+def shift_leg(torch, reps: int):
+    """Per-input time shifting (xe_time_shift) of the pathfinder frame with
+    delays in [-8, 8] samples and its bursty flags moved along: frame and
+    flags read and written once against HBM."""
+    import numpy as np
+    from paper_1503_06189_amd import synth, xengine
+    dev = torch.device("cuda:0")
+    h = xengine.default_handle(0)
+    stream = torch.cuda.current_stream()
+    fr = synth.pathfinder()
+    rng = np.random.default_rng(31)
+    flags = synth.fengine_flags(rng, fr.T, fr.F, fr.N, 1e-3)
+    delays = torch.from_numpy(rng.integers(-8, 9, fr.N).astype(np.int32)).to(dev)
+    packed = torch.from_numpy(fr.packed).to(dev)
+    fl = torch.from_numpy(flags.view(np.int32)).to(dev)
+    out, fo = xengine.time_shift(packed, delays, fl, handle=h, stream=stream)
+    for _ in range(3):
+        xengine.time_shift(packed, delays, fl, out, fo, handle=h, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, 2)
+    e0.record(stream)
+    for _ in range(reps):
+        xengine.time_shift(packed, delays, fl, out, fo, handle=h, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    alg = 2 * (packed.numel() + fl.numel() * 4)
+    gbps = alg / (ms / 1e3) / 1e9
+    return {
+        "workload": f"{fr.name}, delays in [-8, 8] samples, bursty flags 0.1%",
+        "time_shift_us": round(ms * 1e3, 2),
+        "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                     "alg_bytes": int(alg)},
+    }
+
+
 def serving_leg(torch, seconds: float):
     from paper_1503_06189_amd import serve, synth
     specs = synth.streaming_streams()
@@ -354,6 +393,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-flags", action="store_true")
     ap.add_argument("--no-assembly", action="store_true")
+    ap.add_argument("--no-shift", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 256 MiB once (a kernel of known "
@@ -464,6 +504,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_assembly:
         res["assembly"] = assembly_leg(torch, reps=max(5, min(50, args.steps)))
+        torch.cuda.empty_cache()
+    if not args.no_shift:
+        res["shift"] = shift_leg(torch, reps=max(5, min(50, args.steps)))
         torch.cuda.empty_cache()
     if not args.no_serving:
         res["serving"] = serving_leg(torch, args.serve_seconds)

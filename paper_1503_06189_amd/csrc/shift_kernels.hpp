@@ -15,57 +15,159 @@
 namespace xe {
 namespace shift {
 
-// One thread per 4 inputs of one (sample, channel): four byte gathers, one
-// dword store (kVec: N % 4 == 0 and both frames 4-byte aligned), else one
-// byte per thread.
+// A workgroup takes channel f, output samples [t0, t0 + 32) and
+// inputs [i0, i0 + 256).  When the tile's delays span at most kSpan samples,
+// the source rows it needs (32 + span rows of up to 256 bytes and 8 flag
+// words) are staged in LDS with coalesced loads; every output byte is then
+// a read from LDS, and every output flag word one ballot over the 32 lanes
+// of its inputs.  Wider spans fall back to direct gathers in the same
+// workgroup.  Every output element of the tile is written.
+constexpr int kRows = 32;
+constexpr int kCols = 256;
+constexpr int kSpan = 32;
+constexpr int kTileThreads = 256;
+
+// kVec: N % 16 == 0 and both frames 16-byte aligned: rows are staged with
+// 16-byte loads and output bytes are written as dwords.
 template <bool kVec>
-__global__ void data_kernel(const uint8_t *in, const int32_t *delays, uint8_t *out, int N,
-                            int F, int T) {
-    const int per = kVec ? N / 4 : N;
-    const int64_t total = (int64_t)T * F * per;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
-        const int g = (int)(e % per);
-        const int64_t tf = e / per;
-        const int f = (int)(tf % F);
-        const int64_t t = tf / F;
+__global__ __launch_bounds__(kTileThreads) void tile_kernel(const uint8_t *in,
+                                                             const uint32_t *flags_in,
+                                                             const int32_t *delays, uint8_t *out,
+                                                             uint32_t *flags_out, int N, int F,
+                                                             int T, int W) {
+    __shared__ __attribute__((aligned(16))) uint8_t rows[kRows + kSpan][kCols];
+    __shared__ uint32_t frows[kRows + kSpan][kCols / 32];
+    __shared__ int32_t dl[kCols];
+    __shared__ int32_t red[2][kTileThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i_tiles = (N + kCols - 1) / kCols, t_tiles = (T + kRows - 1) / kRows;
+    int64_t b = blockIdx.x;
+    const int it = (int)(b % i_tiles);
+    b /= i_tiles;
+    const int tt = (int)(b % t_tiles);
+    const int f = (int)(b / t_tiles);
+    const int i0 = it * kCols, t0 = tt * kRows;
+    const int ni = min(kCols, N - i0), nt = min(kRows, T - t0);
+
+    // the tile's delays and their range
+    int d = tid < ni ? delays[i0 + tid] : 0;
+    dl[tid] = d;
+    int lo = tid < ni ? d : INT32_MAX, hi = tid < ni ? d : INT32_MIN;
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o));
+        hi = max(hi, __shfl_xor(hi, o));
+    }
+    if (lane == 0) {
+        red[0][wave] = lo;
+        red[1][wave] = hi;
+    }
+    __syncthreads();
+    lo = red[0][0];
+    hi = red[1][0];
+    for (int k = 1; k < kTileThreads / 64; ++k) {
+        lo = min(lo, red[0][k]);
+        hi = max(hi, red[1][k]);
+    }
+    const bool staged = (int64_t)hi - lo <= kSpan;
+    // source rows t - d for t in [t0, t0 + nt) and d in [lo, hi]: [t0 - hi, t0 + nt - 1 - lo]
+    const int64_t s0 = (int64_t)t0 - hi;
+    const int nrows = staged ? nt + (hi - lo) : 0;
+    const int wbase = i0 / 32, nw = (ni + 31) / 32;
+
+    if (staged) {
         if (kVec) {
+            // ni is a multiple of 16 here
+            const int pieces = ni / 16;
+            for (int e = tid; e < nrows * pieces; e += kTileThreads) {
+                const int r = e / pieces, q = e % pieces;
+                const int64_t src = s0 + r;
+                uint4 v = {0u, 0u, 0u, 0u};
+                if (src >= 0 && src < T)
+                    v = *(const uint4 *)(in + (src * F + f) * N + i0 + 16 * q);
+                *(uint4 *)&rows[r][16 * q] = v;
+            }
+        } else {
+            for (int e = tid; e < nrows * kCols; e += kTileThreads) {
+                const int r = e / kCols, c = e % kCols;
+                const int64_t src = s0 + r;
+                rows[r][c] = (c < ni && src >= 0 && src < T) ? in[(src * F + f) * N + i0 + c] : 0;
+            }
+        }
+        if (flags_out)
+            for (int e = tid; e < nrows * (kCols / 32); e += kTileThreads) {
+                const int r = e / (kCols / 32), w = e % (kCols / 32);
+                const int64_t src = s0 + r;
+                frows[r][w] = (flags_in && w < nw && src >= 0 && src < T)
+                                  ? flags_in[((int64_t)f * T + src) * W + wbase + w]
+                                  : 0u;
+            }
+        __syncthreads();
+    }
+
+    // data: thread -> (row, 4 inputs), one dword each (kVec), else one byte
+    if (kVec) {
+        const int quads = ni / 4;
+        for (int e = tid; e < nt * quads; e += kTileThreads) {
+            const int r = e / quads, g = e % quads;
+            const int t = t0 + r;
             uint32_t v = 0;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int i = 4 * g + c;
-                const int64_t src = t - delays[i];
-                const uint32_t b = (src >= 0 && src < T) ? in[(src * F + f) * N + i] : 0x88u;
-                v |= b << (8 * c);
+            for (int k = 0; k < 4; ++k) {
+                const int c = 4 * g + k;
+                const int64_t src = (int64_t)t - dl[c];
+                uint32_t byte = 0x88u;
+                if (src >= 0 && src < T)
+                    byte = staged ? rows[(int)(src - s0)][c] : in[(src * F + f) * N + i0 + c];
+                v |= byte << (8 * k);
             }
-            *(uint32_t *)(out + (t * F + f) * N + 4 * g) = v;
-        } else {
-            const int64_t src = t - delays[g];
-            out[(t * F + f) * N + g] = (src >= 0 && src < T) ? in[(src * F + f) * N + g]
-                                                             : (uint8_t)0x88;
+            *(uint32_t *)(out + ((int64_t)t * F + f) * N + i0 + 4 * g) = v;
         }
+    } else
+    for (int e = tid; e < nt * kCols; e += kTileThreads) {
+        const int r = e / kCols, c = e % kCols;
+        if (c >= ni) continue;
+        const int t = t0 + r;
+        const int64_t src = (int64_t)t - dl[c];
+        uint8_t v = 0x88;
+        if (src >= 0 && src < T)
+            v = staged ? rows[(int)(src - s0)][c] : in[(src * F + f) * N + i0 + c];
+        out[((int64_t)t * F + f) * N + i0 + c] = v;
     }
-}
-
-// One thread per flag word: bit b (input 32 w + b < N) is the source
-// sample's F-engine flag, or 1 when the source lies outside the frame.
-__global__ void flag_kernel(const uint32_t *flags_in, const int32_t *delays, uint32_t *flags_out,
-                            int N, int F, int T, int W) {
-    const int64_t total = (int64_t)F * T * W;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
-        const int w = (int)(e % W);
-        const int64_t ft = e / W;
-        const int64_t t = ft % T, f = ft / T;
-        uint32_t v = 0;
-        for (int b = 0; b < 32 && 32 * w + b < N; ++b) {
-            const int64_t src = t - delays[32 * w + b];
-            uint32_t bit = 1u;
-            if (src >= 0 && src < T)
-                bit = flags_in ? (flags_in[(f * T + src) * W + w] >> b) & 1u : 0u;
-            v |= bit << b;
+    // flags: one output word per 32 lanes (a ballot), two per wave and
+    // four such pairs per iteration (their LDS reads overlap)
+    if (flags_out) {
+        const int half = lane >> 5, bit = lane & 31;
+        constexpr int kStride = (kTileThreads / 64) * 2;
+        for (int e0 = wave * 2 + half; e0 < nt * nw; e0 += 4 * kStride) {
+            bool set[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * kStride;
+                set[u] = false;
+                if (e >= nt * nw) continue;
+                const int r = e / nw, w = e % nw;
+                const int c = 32 * w + bit;
+                if (c >= ni) continue;
+                const int64_t src = (int64_t)(t0 + r) - dl[c];
+                if (src < 0 || src >= T) {
+                    set[u] = true;
+                } else if (flags_in) {
+                    const uint32_t word = staged ? frows[(int)(src - s0)][w]
+                                                 : flags_in[((int64_t)f * T + src) * W + wbase + w];
+                    set[u] = (word >> bit) & 1u;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * kStride;
+                const unsigned long long m = __ballot(set[u]);
+                if (bit == 0 && e < nt * nw) {
+                    const int r = e / nw, w = e % nw;
+                    flags_out[((int64_t)f * T + t0 + r) * W + wbase + w] =
+                        (uint32_t)(m >> (32 * half));
+                }
+            }
         }
-        flags_out[e] = v;
     }
 }
 

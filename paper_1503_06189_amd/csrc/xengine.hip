@@ -761,22 +761,17 @@ xe_status xe_time_shift(xe_handle h, const uint8_t *packed_in, const uint32_t *f
     if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
-    hipStream_t st = (hipStream_t)stream;
-    const bool vec = N % 4 == 0 && aligned(packed_in, 4) && aligned(packed_out, 4);
-    const int64_t items = (int64_t)T * F * (vec ? N / 4 : N);
-    const unsigned blocks = (unsigned)std::min<int64_t>((items + 255) / 256, 65536);
-    if (vec)
-        hipLaunchKernelGGL(xe::shift::data_kernel<true>, dim3(blocks), dim3(256), 0, st,
-                           packed_in, delays, packed_out, N, F, T);
+    using namespace xe::shift;
+    const int64_t tiles =
+        (int64_t)F * ((T + kRows - 1) / kRows) * ((N + kCols - 1) / kCols);
+    if (N % 16 == 0 && aligned(packed_in, 16) && aligned(packed_out, 16))
+        hipLaunchKernelGGL(tile_kernel<true>, dim3((unsigned)tiles), dim3(kTileThreads), 0,
+                           (hipStream_t)stream, packed_in, flags_in, delays, packed_out,
+                           flags_out, N, F, T, W);
     else
-        hipLaunchKernelGGL(xe::shift::data_kernel<false>, dim3(blocks), dim3(256), 0, st,
-                           packed_in, delays, packed_out, N, F, T);
-    if (flags_out) {
-        const int64_t words = (int64_t)F * T * W;
-        hipLaunchKernelGGL(xe::shift::flag_kernel,
-                           dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65536)),
-                           dim3(256), 0, st, flags_in, delays, flags_out, N, F, T, W);
-    }
+        hipLaunchKernelGGL(tile_kernel<false>, dim3((unsigned)tiles), dim3(kTileThreads), 0,
+                           (hipStream_t)stream, packed_in, flags_in, delays, packed_out,
+                           flags_out, N, F, T, W);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "time shift launch");
     return XE_OK;
