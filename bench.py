@@ -372,7 +372,9 @@ def serving_leg(torch, seconds: float):
         "p99_ms": round(st["p99_ms"], 3),
         "frames": st["frames"],
         "offered_gbps": round(st["offered_gbps"], 1),
-        "sustained_gbps": round(st["gbps"], 1),
+        "offered_realized_gbps": round(st["offered_realized_gbps"], 1),
+        "arrival_span_s": round(st["arrival_span_s"], 3),
+        "sustained_gbps": round(st["gbps"], 1),   # served bits / wall (arrival span + drain)
         "mean_batch": round(st["mean_batch"], 2),
         "hbm_budget_bytes": st["hbm_budget"],
         "hbm_peak_used_bytes": st["hbm_peak_used"],

@@ -443,6 +443,12 @@ def run_load(specs, frames_per_stream: Optional[int] = None, integrations: int =
     st["wall_s"] = wall
     st["offered_gbps"] = (sum(s.rate_bps for s in specs) * speed / 1e9
                           if np.isfinite(speed) else None)
+    # what the Poisson draw actually offered: its bytes over the span of the
+    # arrivals (a finite draw's last arrival falls before or after duration)
+    span = arrivals[-1][0] if arrivals else 0.0
+    bits = sum(8.0 * s.N * s.F * s.T * len(sequence[s.stream_id]) for s in specs)
+    st["offered_realized_gbps"] = bits / span / 1e9 if span > 0 else None
+    st["arrival_span_s"] = span
     st["device_resident"] = device_resident
     return LoadResult(server, st, pool, sequence)
 
