@@ -28,6 +28,9 @@ Prints ONE JSON line.  Fields beyond the common ones:
                 packets (1% dropped, 0.5% duplicated, reordered) against HBM
   shift         per-input time shifting of the same frame and its flags
                 against HBM
+  pipeline      one frame through the whole GPU data flow: packets ->
+                assembly -> zeroing of flagged points -> correlation -> flag
+                intersections -> per-baseline normalisation
   serving       8 streams of 4096-sample frames offered with Poisson
                 arrivals at 51.2 Gb/s in total from pinned host memory:
                 p50/p99 frame latency (arrival to accumulated); plus the
@@ -356,6 +359,64 @@ def shift_leg(torch, reps: int):
     }
 
 
+def pipeline_leg(torch, reps: int):
+    """One frame through the whole data flow on the GPU: F-engine packets
+    already in HBM (1% dropped, 0.5% duplicated, reordered, 0.1% bursty
+    per-input flags) -> frame assembly -> zeroing of flagged points ->
+    correlation into the integration -> flag intersections -> per-baseline
+    normalisation.  The integrated counts are checked against a second
+    integration of the same frame (determinism)."""
+    import numpy as np
+    from paper_1503_06189_amd import synth, xengine
+    dev = torch.device("cuda:0")
+    h = xengine.default_handle(0)
+    stream = torch.cuda.current_stream()
+    fr = synth.pathfinder(p_loss=0.0)
+    N, F, T = fr.N, fr.F, fr.T
+    rng = np.random.default_rng(55)
+    flags = synth.fengine_flags(rng, T, F, N, 1e-3)
+    pk = synth.network_faults(rng, synth.packetize(fr.packed, flags), p_drop=0.01,
+                              p_dup=0.005, window=64)
+    dpk = torch.from_numpy(pk).to(dev)
+    S = F // 8
+    packed, mask, fl, stats = xengine.assemble_frame(dpk, N, S, 0, 0, T, handle=h, stream=stream)
+    vis, cnt = xengine.new_accumulators(N, F, dev)
+    dcount = xengine.new_flag_counts(N, F, dev)
+    out = torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.float32, device=dev)
+
+    def frame():
+        xengine.assemble_frame(dpk, N, S, 0, 0, T, packed, mask, fl, stats, handle=h,
+                               stream=stream)
+        xengine.apply_flags(packed, fl, handle=h, stream=stream)
+        xengine.accumulate(packed, mask, 4, vis, cnt, handle=h, stream=stream)
+        xengine.flag_accumulate(fl, mask, 4, N, dcount, handle=h, stream=stream)
+        xengine.normalize_flagged(vis, cnt, dcount, out=out, handle=h, stream=stream)
+
+    frame()
+    torch.cuda.synchronize()
+    one = (vis.clone(), cnt.clone(), dcount.clone())
+    for _ in range(2):
+        frame()
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, 2)
+    e0.record(stream)
+    for _ in range(reps):
+        frame()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    k = 3 + reps
+    exact = (torch.equal(vis, one[0] * k) and torch.equal(cnt, one[1] * k)
+             and torch.equal(dcount, one[2] * k))
+    return {
+        "workload": f"{fr.name} from {len(pk)} packets: assemble, zero flagged points, "
+                    "correlate, flag intersections, per-baseline normalise",
+        "frame_ms": round(ms, 4),
+        "gbps": round(8.0 * N * F * T / (ms / 1e3) / 1e9, 1),
+        "integration_exact": bool(exact),
+    }
+
+
 def serving_leg(torch, seconds: float):
     from paper_1503_06189_amd import serve, synth
     specs = synth.streaming_streams()
@@ -396,6 +457,7 @@ def main():
     ap.add_argument("--no-flags", action="store_true")
     ap.add_argument("--no-assembly", action="store_true")
     ap.add_argument("--no-shift", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 256 MiB once (a kernel of known "
@@ -509,6 +571,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_shift:
         res["shift"] = shift_leg(torch, reps=max(5, min(50, args.steps)))
+        torch.cuda.empty_cache()
+    if not args.no_pipeline:
+        res["pipeline"] = pipeline_leg(torch, reps=max(5, min(30, args.steps)))
         torch.cuda.empty_cache()
     if not args.no_serving:
         res["serving"] = serving_leg(torch, args.serve_seconds)

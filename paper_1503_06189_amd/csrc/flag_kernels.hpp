@@ -150,13 +150,23 @@ __device__ __forceinline__ void fill_window(const Args &a, Lds<SIDES> &L, int f,
         const int n = min(32, t_end - t);
         uint32_t bits = n == 32 ? 0xffffffffu : (1u << n) - 1u;
         if (a.mask) {
+            // the blocks touching the word's samples, eight loads at a time,
+            // all issued before the first is used (indices clamped)
             const uint8_t *row = a.mask + (int64_t)f * a.nblk;
-            for (int b = block_of(a, t), last = block_of(a, t + n - 1); b <= last; ++b) {
-                if (row[b] == 0) continue;
-                const int lo = max(t, b * a.B) - t;
-                const int hi = min(t + n, (b + 1) * a.B) - t;        // exclusive
-                const uint64_t span = ((1ull << hi) - 1ull) & ~((1ull << lo) - 1ull);
-                bits &= ~(uint32_t)span;
+            const int first = block_of(a, t), last = block_of(a, t + n - 1);
+            for (int b0 = first; b0 <= last; b0 += 8) {
+                uint32_t v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = row[min(b0 + q, last)];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int b = b0 + q;
+                    if (b > last || v[q] == 0u) continue;
+                    const int lo = max(t, b * a.B) - t;
+                    const int hi = min(t + n, (b + 1) * a.B) - t;    // exclusive
+                    const uint64_t span = ((1ull << hi) - 1ull) & ~((1ull << lo) - 1ull);
+                    bits &= ~(uint32_t)span;
+                }
             }
         }
         L.valid[s] = bits;

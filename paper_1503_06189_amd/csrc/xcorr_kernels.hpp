@@ -526,16 +526,28 @@ __device__ __forceinline__ T *partial_tiles(T *partials, int64_t key, int splits
            (int64_t)wave * kWavePartial;
 }
 
-// valid samples of channel f in [t0, t1)
-__device__ inline int64_t valid_count(const CorrArgs &a, int f, int t0, int t1) {
-    if (a.mask == nullptr) return t1 - t0;
-    int64_t n = 0;
-    for (int b = t0 / a.B; (int64_t)b * a.B < t1; ++b) {
-        int64_t lo = (int64_t)b * a.B, hi = lo + a.B;
-        if (lo < t0) lo = t0;
-        if (hi > t1) hi = t1;
-        if (a.mask[(int64_t)f * a.nblk_mask + b] == 0) n += hi - lo;
+// Valid samples of one channel (mask row m of nblk blocks of B samples, T
+// samples), counted by one wave: lane l takes blocks l, l + 64, ..., four
+// per pass with every load issued before the first is used (indices clamped
+// in range), then the lanes' sums are added; every lane gets the total.
+__device__ inline int64_t valid_count(const uint8_t *m, int nblk, int B, int T, int lane) {
+    if (m == nullptr) return T;
+    const int last = nblk - 1;
+    int n = 0;  // <= T < 2^24
+    for (int b0 = 0; b0 <= last; b0 += 64 * 4) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = m[min(b0 + 64 * u + lane, last)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + 64 * u + lane;
+            const int64_t lo = (int64_t)b * B;
+            const int64_t hi = lo + B < T ? lo + B : T;
+            n += (b <= last && v[u] == 0u) ? (int)(hi - lo) : 0;
+        }
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
     return n;
 }
 
@@ -718,10 +730,6 @@ __device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int 
                 *(v2i *)(visf + 2 * idx) = kOverwrite ? val : old[v] + val;
             }
         }
-    }
-    if (gid == 0 && threadIdx.x == 0) {
-        int64_t n = valid_count(a, f, 0, a.T);
-        a.count[f] = kOverwrite ? n : a.count[f] + n;
     }
 }
 
@@ -938,6 +946,37 @@ __global__ __launch_bounds__(64) void merge_list_kernel(const MergeInst *list, i
     }
     const MergeInst m = list[lo];
     merge_block(m, b - m.block_begin);
+}
+
+// ---------------------------------------------------------------------------
+// valid-sample counts (the packet-loss counter, Sec. II-C)
+// ---------------------------------------------------------------------------
+
+// One wave per channel of one frame; a separate launch, so that the
+// correlation kernel's registers stay with its main loop.
+constexpr int kCountWaves = 4;
+
+__global__ __launch_bounds__(64 * kCountWaves) void count_kernel(const uint8_t *mask, int nblk,
+                                                                 int B, int T, int F,
+                                                                 int64_t *count, int overwrite) {
+    const int lane = threadIdx.x & 63;
+    const int f = blockIdx.x * kCountWaves + (threadIdx.x >> 6);
+    if (f >= F) return;
+    const int64_t n = valid_count(mask ? mask + (int64_t)f * nblk : nullptr, nblk, B, T, lane);
+    if (lane == 0) count[f] = overwrite ? n : count[f] + n;
+}
+
+// The same for every instance of a batch (block b = instance b, its waves
+// take its channels in turn); batches accumulate.
+__global__ __launch_bounds__(64 * kCountWaves) void count_list_kernel(const BatchInstance *inst,
+                                                                      int n_inst) {
+    const BatchInstance &x = inst[blockIdx.x];
+    const int lane = threadIdx.x & 63;
+    for (int f = threadIdx.x >> 6; f < x.F; f += kCountWaves) {
+        const int64_t n = valid_count(x.mask ? x.mask + (int64_t)f * x.nblk_mask : nullptr,
+                                      x.nblk_mask, x.B, x.T, lane);
+        if (lane == 0) x.count[f] += n;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -185,6 +185,12 @@ xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, i
         hipLaunchKernelGGL((xe::corr_kernel<false, true>), grid, block, 0, stream, a);
     else
         hipLaunchKernelGGL((xe::corr_kernel<false, false>), grid, block, 0, stream, a);
+    // the valid-sample counts in a launch of their own, so that the
+    // correlation kernel's registers stay with its main loop
+    hipLaunchKernelGGL(xe::count_kernel,
+                       dim3((unsigned)((F + xe::kCountWaves - 1) / xe::kCountWaves)),
+                       dim3(64 * xe::kCountWaves), 0, stream, mask, a.nblk_mask, B, T, F, count,
+                       overwrite ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "correlation launch");
     if (p.splits > 1) {
@@ -379,6 +385,8 @@ xe_status launch_batch(xe_handle h, int slot, const SlotShape &sh, hipStream_t s
     int grid = std::min(h->n_cu, sh.n_items);
     hipLaunchKernelGGL(xe::batch_kernel, dim3(grid), dim3(xe::kThreads), 0, stream, bi, items,
                        sh.n_items, (int *)base, (int32_t *)h->workspace);
+    hipLaunchKernelGGL(xe::count_list_kernel, dim3((unsigned)sh.n_inst),
+                       dim3(64 * xe::kCountWaves), 0, stream, bi, sh.n_inst);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "batch launch");
     if (sh.n_merges > 0) {
