@@ -105,6 +105,39 @@ def cpu_baseline(fr, target_s: float):
         "kind": "oracle",
         "sample": f"{n_ch} of {fr.F} channels, full {fr.T} samples, N={fr.N} "
                   f"({dt:.1f} s of CPU work)",
+        "next_paths": cpu_baseline_next(orc, fr),
+    }
+
+
+def cpu_baseline_next(orc, fr):
+    """The oracle's other paths on the same frame, one host thread each
+    (their loops are not parallelised): flag counters and intersections
+    (bursty 0.1% flags, all 64 channels), frame assembly from the frame's
+    packets with faults, and the time shift of the first 8 channels; each
+    as microseconds per pathfinder frame, to set beside the GPU legs."""
+    import numpy as np
+    from paper_1503_06189_amd import synth
+    rng = np.random.default_rng(2024)
+    flags = synth.fengine_flags(rng, fr.T, fr.F, fr.N, 1e-3, mean_run=32.0)
+    t0 = time.perf_counter()
+    orc.flag_counters(flags, fr.mask, fr.N, fr.B)
+    flag_s = time.perf_counter() - t0
+    pk = synth.network_faults(rng, synth.packetize(fr.packed, flags), p_drop=0.01,
+                              p_dup=0.005, window=64)
+    t0 = time.perf_counter()
+    orc.assemble(pk, fr.N, fr.F // 8, 0, 0, fr.T)
+    asm_s = time.perf_counter() - t0
+    n_ch = 8
+    d = rng.integers(-8, 9, fr.N).astype(np.int32)
+    t0 = time.perf_counter()
+    orc.time_shift(np.ascontiguousarray(fr.packed[:, :n_ch]),
+                   np.ascontiguousarray(flags[:n_ch]), d)
+    shift_s = (time.perf_counter() - t0) * fr.F / n_ch
+    return {
+        "flag_counters_us_per_frame": round(flag_s * 1e6, 1),
+        "assemble_us_per_frame": round(asm_s * 1e6, 1),
+        "time_shift_us_per_frame": round(shift_s * 1e6, 1),
+        "sample": f"{fr.name}; time shift timed on {n_ch} of {fr.F} channels and scaled",
     }
 
 
