@@ -930,7 +930,27 @@ __device__ __forceinline__ void merge_block(const MergeInst &m, int64_t b) {
 }
 
 // one instance: F * groups * 8 * kTilesPerWave blocks of one wave
-__global__ __launch_bounds__(64) void merge_kernel(MergeInst m) { merge_block(m, blockIdx.x); }
+// Valid-sample counts of a frame, taken by extra blocks of its merge launch
+// (block first_block + f counts channel f), so a chunked frame needs no
+// launch of its own for them.
+struct CountArgs {
+    const uint8_t *mask;
+    int64_t *count;
+    int nblk, B, T, overwrite;
+    int64_t first_block;
+};
+
+__global__ __launch_bounds__(64) void merge_kernel(MergeInst m, CountArgs c) {
+    if ((int64_t)blockIdx.x >= c.first_block) {
+        const int f = (int)(blockIdx.x - c.first_block);
+        const int lane = threadIdx.x & 63;
+        const int64_t n = valid_count(c.mask ? c.mask + (int64_t)f * c.nblk : nullptr, c.nblk,
+                                      c.B, c.T, lane);
+        if (lane == 0) c.count[f] = c.overwrite ? n : c.count[f] + n;
+        return;
+    }
+    merge_block(m, blockIdx.x);
+}
 
 // a batch's chunked instances, sorted by block_begin; block b belongs to the
 // last instance whose first block is <= b

@@ -185,12 +185,14 @@ xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, i
         hipLaunchKernelGGL((xe::corr_kernel<false, true>), grid, block, 0, stream, a);
     else
         hipLaunchKernelGGL((xe::corr_kernel<false, false>), grid, block, 0, stream, a);
-    // the valid-sample counts in a launch of their own, so that the
-    // correlation kernel's registers stay with its main loop
-    hipLaunchKernelGGL(xe::count_kernel,
-                       dim3((unsigned)((F + xe::kCountWaves - 1) / xe::kCountWaves)),
-                       dim3(64 * xe::kCountWaves), 0, stream, mask, a.nblk_mask, B, T, F, count,
-                       overwrite ? 1 : 0);
+    // The valid-sample counts run outside the correlation kernel, so that
+    // its registers stay with its main loop: in extra blocks of the merge
+    // launch when the frame is chunked, else in a launch of their own.
+    if (p.splits == 1)
+        hipLaunchKernelGGL(xe::count_kernel,
+                           dim3((unsigned)((F + xe::kCountWaves - 1) / xe::kCountWaves)),
+                           dim3(64 * xe::kCountWaves), 0, stream, mask, a.nblk_mask, B, T, F,
+                           count, overwrite ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "correlation launch");
     if (p.splits > 1) {
@@ -204,8 +206,17 @@ xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, i
         m.splits = p.splits;
         m.block_begin = 0;
         const int64_t blocks = (int64_t)F * p.groups * xe::kMergeBlocksPerGroup;
-        if (blocks > 0x7fffffff) return fail(h, XE_ERR_ARG, "too many merge blocks");
-        hipLaunchKernelGGL(xe::merge_kernel, dim3((unsigned)blocks), dim3(64), 0, stream, m);
+        if (blocks + F > 0x7fffffff) return fail(h, XE_ERR_ARG, "too many merge blocks");
+        xe::CountArgs c;
+        c.mask = mask;
+        c.count = count;
+        c.nblk = a.nblk_mask;
+        c.B = B;
+        c.T = T;
+        c.overwrite = overwrite ? 1 : 0;
+        c.first_block = blocks;
+        hipLaunchKernelGGL(xe::merge_kernel, dim3((unsigned)(blocks + F)), dim3(64), 0, stream, m,
+                           c);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(h, e, "merge launch");
     }
