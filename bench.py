@@ -193,12 +193,14 @@ def batched_leg(torch, reps: int):
     for _, _, _, v, c in items:
         v.zero_()
         c.zero_()
+        xengine.reset_integration(v)
     plain()
     torch.cuda.synchronize()
     want = [(v.clone(), c.clone()) for _, _, _, v, c in items]
     for _, _, _, v, c in items:
         v.zero_()
         c.zero_()
+        xengine.reset_integration(v)
     g.replay()
     torch.cuda.synchronize()
     exact = all(torch.equal(v, w) and torch.equal(c, n)
@@ -532,6 +534,7 @@ def main():
     torch.cuda.synchronize()
     vis.zero_()
     cnt.zero_()
+    xengine.reset_integration(vis)
     torch.cuda.synchronize()
 
     k_ev = [tuple(_events(torch, 2)) for _ in range(args.steps)]

@@ -284,6 +284,7 @@ class StreamServer:
             with torch.cuda.stream(cs):
                 s.acc[nk][0].zero_()
                 s.acc[nk][1].zero_()
+                xengine.reset_integration(s.acc[nk][0])
         return True
 
     def _complete(self) -> int:

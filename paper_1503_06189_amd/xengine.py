@@ -48,6 +48,43 @@ class XEngineError(RuntimeError):
         self.status = status
 
 
+# Samples integrated into each accumulator since it was last cleared, keyed by
+# the sums' device address.  int32 sums are exact for at most XE_MAX_SAMPLES
+# accumulated samples (|Re V| <= 128 per sample); calls that would pass that
+# bound are refused before launching.  correlate_frame and new_accumulators
+# start a count; callers that clear sums themselves call reset_integration.
+# Replays of a captured graph bypass this bookkeeping.
+_integrated = {}
+_integrated_lock = threading.Lock()
+
+
+def reset_integration(vis) -> None:
+    """Mark the sums in ``vis`` as cleared (0 samples integrated)."""
+    with _integrated_lock:
+        _integrated[vis.data_ptr()] = 0
+
+
+def integrated_samples(vis) -> int:
+    """Samples integrated into ``vis`` since it was last cleared."""
+    with _integrated_lock:
+        return _integrated.get(vis.data_ptr(), 0)
+
+
+def _charge(pairs) -> None:
+    """Add T samples to each (vis, T); refuse all if one would pass the bound."""
+    with _integrated_lock:
+        new = {}
+        for vis, T in pairs:
+            key = vis.data_ptr()
+            n = new.get(key, _integrated.get(key, 0)) + int(T)
+            if n > XE_MAX_SAMPLES:
+                raise XEngineError(XE_ERR_OVERFLOW,
+                                   f"{n} samples would exceed the int32 integration bound "
+                                   f"{XE_MAX_SAMPLES}; normalise and clear the sums first")
+            new[key] = n
+        _integrated.update(new)
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("blocks", ctypes.c_int32), ("groups", ctypes.c_int32),
                 ("splits", ctypes.c_int32), ("steps_per_split", ctypes.c_int32),
@@ -216,8 +253,9 @@ def new_accumulators(N: int, F: int, device=None):
     import torch
     P = N * (N + 1) // 2
     dev = device if device is not None else torch.device("cuda")
-    return (torch.zeros((F, P, 2), dtype=torch.int32, device=dev),
-            torch.zeros((F,), dtype=torch.int64, device=dev))
+    vis = torch.zeros((F, P, 2), dtype=torch.int32, device=dev)
+    reset_integration(vis)
+    return vis, torch.zeros((F,), dtype=torch.int64, device=dev)
 
 
 def _check_acc(vis, count, N, F):
@@ -242,6 +280,8 @@ def correlate_frame(packed, mask=None, B: int = 256, vis=None, count=None,
         ctypes.c_void_p(mask.data_ptr() if mask is not None else None),
         N, F, T, B, ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(count.data_ptr()),
         _stream_ptr(stream)))
+    with _integrated_lock:
+        _integrated[vis.data_ptr()] = T
     return vis, count
 
 
@@ -250,6 +290,7 @@ def accumulate(packed, mask, B: int, vis, count, handle: Optional[Handle] = None
     """vis += V(frame), count += n(frame), in place on the device."""
     T, F, N = _check_frame(packed, mask, B)
     _check_acc(vis, count, N, F)
+    _charge([(vis, T)])
     h = handle or default_handle(packed.device.index)
     h.check(lib().xe_accumulate(
         h.ptr, ctypes.c_void_p(packed.data_ptr()),
@@ -455,6 +496,7 @@ def _instances(items: Sequence[Tuple]):
 def accumulate_batch(items: Sequence[Tuple], handle: Optional[Handle] = None, stream=None):
     """items: (packed, mask, B, vis, count) per instance; one persistent launch."""
     arr, dev = _instances(items)
+    _charge([(v, p.shape[0]) for p, m, B, v, c in items])
     h = handle or default_handle(dev)
     h.check(lib().xe_accumulate_batch(h.ptr, arr, len(items), _stream_ptr(stream)))
 
@@ -475,6 +517,7 @@ class BatchPlan:
         self.plan_id = pid.value
 
     def run(self, stream=None) -> None:
+        _charge([(v, p.shape[0]) for p, m, B, v, c in self.items])
         self.handle.check(lib().xe_batch_run(self.handle.ptr, self.plan_id,
                                              _stream_ptr(stream)))
 

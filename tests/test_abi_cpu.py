@@ -297,3 +297,22 @@ def test_time_shift_checks(L, h):
     assert sh(fout=0x200000 + 4) == xe.XE_ERR_ARG        # overlaps the input flags
     assert sh(d=0x300002) == xe.XE_ERR_ALIGN
     assert sh(fout=0x500002) == xe.XE_ERR_ALIGN
+
+
+def test_integration_bound_bookkeeping():
+    """Samples integrated per accumulator are counted and a call that would
+    pass the int32 bound is refused before anything is launched."""
+    torch = pytest.importorskip("torch")
+    vis = torch.zeros(4, dtype=torch.int32)
+    other = torch.zeros(4, dtype=torch.int32)
+    xe.reset_integration(vis)
+    xe._charge([(vis, xe.XE_MAX_SAMPLES - 10)])
+    assert xe.integrated_samples(vis) == xe.XE_MAX_SAMPLES - 10
+    xe._charge([(vis, 10)])                      # exactly at the bound: allowed
+    with pytest.raises(xe.XEngineError) as e:
+        xe._charge([(other, 5), (vis, 1)])       # one over: the whole call is refused
+    assert e.value.status == xe.XE_ERR_OVERFLOW
+    assert xe.integrated_samples(other) == 0     # nothing was charged
+    xe.reset_integration(vis)
+    xe._charge([(vis, 1), (vis, 2)])             # the same sums twice in one batch
+    assert xe.integrated_samples(vis) == 3

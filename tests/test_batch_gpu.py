@@ -57,6 +57,8 @@ class Inst:
     def zero(self):
         self.vis.zero_()
         self.cnt.zero_()
+        from paper_1503_06189_amd import xengine
+        xengine.reset_integration(self.vis)
 
 
 def _frames(n_inst, t_scale, n_choices, seed=synth.SEEDS["batched"]):

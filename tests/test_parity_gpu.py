@@ -216,3 +216,23 @@ def test_bad_arguments_raise(xe):
         xe.correlate_frame(packed, torch.zeros((1, 3), dtype=torch.uint8, device="cuda"), 2)
     with pytest.raises(xe.XEngineError):
         xe.correlate_frame(torch.zeros((0, 1, 8), dtype=torch.uint8, device="cuda"), None, 2)
+
+
+def test_integration_bound_refused(xe):
+    """An accumulate that would pass the int32 integration bound raises
+    XE_ERR_OVERFLOW and leaves the sums untouched; correlate_frame starts a
+    new count."""
+    fr = synth.tiny()
+    packed = _dev(fr.packed)
+    vis, cnt = xe.new_accumulators(fr.N, fr.F, packed.device)
+    xe.accumulate(packed, None, fr.B, vis, cnt)
+    torch.cuda.synchronize()
+    before = vis.clone()
+    xe._charge([(vis, xe.XE_MAX_SAMPLES - fr.T - 1)])
+    with pytest.raises(xe.XEngineError) as e:
+        xe.accumulate(packed, None, fr.B, vis, cnt)
+    assert e.value.status == xe.XE_ERR_OVERFLOW
+    torch.cuda.synchronize()
+    assert torch.equal(vis, before)
+    xe.correlate_frame(packed, None, fr.B, vis, cnt)
+    assert xe.integrated_samples(vis) == fr.T
