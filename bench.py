@@ -28,6 +28,8 @@ Prints ONE JSON line.  Fields beyond the common ones:
                 packets (1% dropped, 0.5% duplicated, reordered) against HBM
   shift         per-input time shifting of the same frame and its flags
                 against HBM
+  large_n       N=2048, 16 channels, 8192 samples accumulated, against the
+                int8 MFMA peak
   pipeline      one frame through the whole GPU data flow: packets ->
                 assembly -> zeroing of flagged points -> correlation -> flag
                 intersections -> per-baseline normalisation
@@ -35,7 +37,8 @@ Prints ONE JSON line.  Fields beyond the common ones:
                 arrivals at 51.2 Gb/s in total from pinned host memory:
                 p50/p99 frame latency (arrival to accumulated); plus the
                 serving loop's sustained rate on device-resident frames
-                against one plain launch per frame
+                against one plain launch per frame, and its saturated rate
+                fed from pinned host memory
   cpu_baseline  the oracle (plain C loops) on a bounded sample of the same
                 frame, on this host's cores
 """
@@ -102,11 +105,23 @@ def cpu_baseline(fr, target_s: float):
         "value": round(metrics.input_gbps(fr.N, n_ch, fr.T, dt), 6),
         "unit": "Gb/s",
         "cores": threads,
+        "cpu": _cpu_model(),
         "kind": "oracle",
         "sample": f"{n_ch} of {fr.F} channels, full {fr.T} samples, N={fr.N} "
                   f"({dt:.1f} s of CPU work)",
         "next_paths": cpu_baseline_next(orc, fr),
     }
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline_next(orc, fr):
@@ -452,6 +467,40 @@ def pipeline_leg(torch, reps: int):
     }
 
 
+def large_n_leg(torch, reps: int):
+    """The large-N scaling point: N=2048, 16 channels, 8192 samples, 0.5%
+    block loss, accumulated (xe_accumulate) against the int8 MFMA peak.
+    Uniform random bytes of that shape stand in for the point-source recipe
+    (the correlation's cost does not depend on the values)."""
+    from paper_1503_06189_amd import metrics, synth, xengine
+    dev = torch.device("cuda:0")
+    h = xengine.default_handle(0)
+    stream = torch.cuda.current_stream()
+    fr = synth.random_bytes_frame(synth.SEEDS["large_n"], 2048, 16, 8192, 256, p_loss=0.005,
+                                  fill="zero")
+    packed = torch.from_numpy(fr.packed).to(dev)
+    mask = torch.from_numpy(fr.mask).to(dev)
+    vis, cnt = xengine.new_accumulators(fr.N, fr.F, dev)
+    for _ in range(3):
+        xengine.accumulate(packed, mask, fr.B, vis, cnt, handle=h, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, 2)
+    e0.record(stream)
+    for _ in range(reps):
+        xengine.accumulate(packed, mask, fr.B, vis, cnt, handle=h, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    tops = metrics.int_ops(fr.N, fr.F, fr.T) / (ms / 1e3) / 1e12
+    return {
+        "workload": f"N={fr.N}, F={fr.F}, T={fr.T}, 0.5% block loss (uniform random bytes)",
+        "accumulate_ms": round(ms, 4),
+        "gbps": round(metrics.input_gbps(fr.N, fr.F, fr.T, ms / 1e3), 1),
+        "tops": round(tops, 1),
+        "mfma_frac": round(tops / MFMA_INT8_PEAK_TOPS, 4),
+    }
+
+
 def serving_leg(torch, seconds: float):
     from paper_1503_06189_amd import serve, synth
     specs = synth.streaming_streams()
@@ -460,6 +509,8 @@ def serving_leg(torch, seconds: float):
     sat = serve.run_load(specs, frames_per_stream=12, speed=float("inf"), pool=pool,
                          device_resident=True, hbm_budget=1 << 36)
     plain = serve.run_plain(specs, pool, 12)
+    host_sat = serve.run_load(specs, frames_per_stream=12, speed=float("inf"), pool=pool,
+                              device_resident=False, hbm_budget=1 << 36)
     st = live.stats
     return {
         "workload": "8 streams, N in {128,256,512}, F 16..64, 4096-sample frames, "
@@ -476,6 +527,7 @@ def serving_leg(torch, seconds: float):
         "hbm_peak_used_bytes": st["hbm_peak_used"],
         "device_resident_gbps": round(sat.stats["gbps"], 1),
         "device_resident_plain_gbps": round(plain["gbps"], 1),
+        "host_fed_saturated_gbps": round(host_sat.stats["gbps"], 1),
     }
 
 
@@ -493,6 +545,7 @@ def main():
     ap.add_argument("--no-assembly", action="store_true")
     ap.add_argument("--no-shift", action="store_true")
     ap.add_argument("--no-pipeline", action="store_true")
+    ap.add_argument("--no-large-n", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 256 MiB once (a kernel of known "
@@ -607,6 +660,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_shift:
         res["shift"] = shift_leg(torch, reps=max(5, min(50, args.steps)))
+        torch.cuda.empty_cache()
+    if not args.no_large_n:
+        res["large_n"] = large_n_leg(torch, reps=max(5, min(20, args.steps)))
         torch.cuda.empty_cache()
     if not args.no_pipeline:
         res["pipeline"] = pipeline_leg(torch, reps=max(5, min(30, args.steps)))
