@@ -26,6 +26,7 @@ constexpr int kRows = 32;
 constexpr int kCols = 256;
 constexpr int kSpan = 32;
 constexpr int kTileThreads = 256;
+static_assert(kCols / 32 == 2 * (kTileThreads / 64), "one flag-word column per half-wave");
 
 // kVec: N % 16 == 0 and both frames 16-byte aligned: rows are staged with
 // 16-byte loads and output bytes are written as dwords.
@@ -36,7 +37,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(const uint8_t *in,
                                                              uint32_t *flags_out, int N, int F,
                                                              int T, int W) {
     __shared__ __attribute__((aligned(16))) uint8_t rows[kRows + kSpan][kCols];
-    __shared__ uint32_t frows[kRows + kSpan][kCols / 32];
+    __shared__ uint32_t frows[kRows + kSpan][kCols / 32 + 1];   // padded: rows 9 words apart
     __shared__ int32_t dl[kCols];
     __shared__ int32_t red[2][kTileThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -104,67 +105,87 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(const uint8_t *in,
         __syncthreads();
     }
 
-    // data: thread -> (row, 4 inputs), one dword each (kVec), else one byte
+    // data: thread tid keeps input quad tid % 64 (its 4 delays in registers)
+    // and walks rows tid / 64, +4, ...; one dword each (kVec), else bytes
     if (kVec) {
-        const int quads = ni / 4;
-        for (int e = tid; e < nt * quads; e += kTileThreads) {
-            const int r = e / quads, g = e % quads;
-            const int t = t0 + r;
-            uint32_t v = 0;
+        const int g = tid & 63, quads = ni / 4;
+        if (g < quads) {
+            // per input: rows r of the tile whose source lies in the frame,
+            // rlo <= r < rhi, and the staged row of r, r + base
+            int dk[4], rlo[4], rhi[4], base[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int c = 4 * g + k;
-                const int64_t src = (int64_t)t - dl[c];
-                uint32_t byte = 0x88u;
-                if (src >= 0 && src < T)
-                    byte = staged ? rows[(int)(src - s0)][c] : in[(src * F + f) * N + i0 + c];
-                v |= byte << (8 * k);
+                dk[k] = dl[4 * g + k];
+                const int64_t l = (int64_t)dk[k] - t0, u = (int64_t)T + dk[k] - t0;
+                rlo[k] = (int)(l < 0 ? 0 : (l > nt ? nt : l));
+                rhi[k] = (int)(u < 0 ? 0 : (u > nt ? nt : u));
+                base[k] = hi - dk[k];
             }
-            *(uint32_t *)(out + ((int64_t)t * F + f) * N + i0 + 4 * g) = v;
+            for (int r = tid >> 6; r < nt; r += kTileThreads / 64) {
+                const int t = t0 + r;
+                uint32_t v = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = 4 * g + k;
+                    uint32_t byte = 0x88u;
+                    if (r >= rlo[k] && r < rhi[k])
+                        byte = staged ? rows[r + base[k]][c]
+                                      : in[((int64_t)(t - dk[k]) * F + f) * N + i0 + c];
+                    v |= byte << (8 * k);
+                }
+                *(uint32_t *)(out + ((int64_t)t * F + f) * N + i0 + 4 * g) = v;
+            }
         }
-    } else
-    for (int e = tid; e < nt * kCols; e += kTileThreads) {
-        const int r = e / kCols, c = e % kCols;
-        if (c >= ni) continue;
-        const int t = t0 + r;
-        const int64_t src = (int64_t)t - dl[c];
-        uint8_t v = 0x88;
-        if (src >= 0 && src < T)
-            v = staged ? rows[(int)(src - s0)][c] : in[(src * F + f) * N + i0 + c];
-        out[((int64_t)t * F + f) * N + i0 + c] = v;
+    } else {
+        for (int c = tid; c < ni; c += kTileThreads) {
+            const int dc = dl[c];
+            for (int r = 0; r < nt; ++r) {
+                const int t = t0 + r;
+                const int64_t src = (int64_t)t - dc;
+                uint8_t v = 0x88;
+                if (src >= 0 && src < T)
+                    v = staged ? rows[r + hi - dc][c] : in[(src * F + f) * N + i0 + c];
+                out[((int64_t)t * F + f) * N + i0 + c] = v;
+            }
+        }
     }
-    // flags: one output word per 32 lanes (a ballot), two per wave and
-    // four such pairs per iteration (their LDS reads overlap)
+    // flags: half-wave h (of 8) owns word column h of the tile; lane b holds
+    // input 32 h + b and its delay, and each row's word is one ballot
     if (flags_out) {
         const int half = lane >> 5, bit = lane & 31;
-        constexpr int kStride = (kTileThreads / 64) * 2;
-        for (int e0 = wave * 2 + half; e0 < nt * nw; e0 += 4 * kStride) {
-            bool set[4];
+        const int w = wave * 2 + half;
+        if (w < nw) {
+            const int c = 32 * w + bit;
+            const bool inb = c < ni;
+            const int dc = inb ? dl[c] : 0;
+            const int64_t l = (int64_t)dc - t0, u = (int64_t)T + dc - t0;
+            const int rlo = (int)(l < 0 ? 0 : (l > nt ? nt : l));
+            const int rhi = (int)(u < 0 ? 0 : (u > nt ? nt : u));
+            const int base = hi - dc;
+            // four rows per pass: their reads are in flight together
+            for (int r0 = 0; r0 < nt; r0 += 4) {
+                bool set[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = e0 + u * kStride;
-                set[u] = false;
-                if (e >= nt * nw) continue;
-                const int r = e / nw, w = e % nw;
-                const int c = 32 * w + bit;
-                if (c >= ni) continue;
-                const int64_t src = (int64_t)(t0 + r) - dl[c];
-                if (src < 0 || src >= T) {
-                    set[u] = true;
-                } else if (flags_in) {
-                    const uint32_t word = staged ? frows[(int)(src - s0)][w]
-                                                 : flags_in[((int64_t)f * T + src) * W + wbase + w];
-                    set[u] = (word >> bit) & 1u;
+                for (int u = 0; u < 4; ++u) {
+                    const int r = r0 + u;
+                    set[u] = false;
+                    if (inb && r < nt) {
+                        if (r < rlo || r >= rhi) {
+                            set[u] = true;
+                        } else if (flags_in) {
+                            const uint32_t word =
+                                staged ? frows[r + base][w]
+                                       : flags_in[((int64_t)f * T + (t0 + r - dc)) * W + wbase + w];
+                            set[u] = (word >> bit) & 1u;
+                        }
+                    }
                 }
-            }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = e0 + u * kStride;
-                const unsigned long long m = __ballot(set[u]);
-                if (bit == 0 && e < nt * nw) {
-                    const int r = e / nw, w = e % nw;
-                    flags_out[((int64_t)f * T + t0 + r) * W + wbase + w] =
-                        (uint32_t)(m >> (32 * half));
+                for (int u = 0; u < 4; ++u) {
+                    const unsigned long long m = __ballot(set[u]);
+                    if (bit == 0 && r0 + u < nt)
+                        flags_out[((int64_t)f * T + t0 + r0 + u) * W + wbase + w] =
+                            (uint32_t)(m >> (32 * half));
                 }
             }
         }
