@@ -16,7 +16,7 @@
 // of word i / 32 = input i.  A workgroup takes one channel, one pair of
 // 256-input super blocks (R <= C) and one chunk of time, in stages of 256
 // samples:
-//   1. the words of both super blocks are loaded several stages ahead (0 for
+//   1. the words of both super blocks are loaded a few stages ahead (0 for
 //      lost samples, samples past the chunk and inputs past N) and stored in
 //      LDS with one "any flag" bit per (32-input block, 32-sample step),
 //      gathered by wave ballots;
@@ -48,7 +48,7 @@ constexpr int kSuper = 8;                // 32-input blocks per super block
 constexpr int kSteps = 8;                // 32-sample steps per stage
 constexpr int kStage = kSteps * 32;      // samples per stage
 constexpr int kPitch = kStage + 4;       // LDS words per block row (16-B aligned rows)
-constexpr int kWindow = 2048;            // validity words per chunk: chunks <= 65536 samples
+constexpr int kWindow = 1024;            // validity words per chunk: chunks <= 32768 samples
 
 struct Args {
     const uint32_t *flags;   // [F][T][W]
@@ -283,11 +283,12 @@ __device__ __forceinline__ void run_role(const Args &a, Lds<SIDES> &L, int f, in
     const Lane<SIDES> ln = make_lane<SIDES>(a, f, R, C, t_begin, t_end, tid);
     fill_window(a, L, f, t_begin, t_end, tid);
     // Stage j's words sit in g[j % D] from D stages ahead until stored (D =
-    // 6 for a diagonal pair, 2 for the register-heavy off-diagonal roles).
+    // 4 for a diagonal pair, two of which share a CU; 2 for the
+    // register-heavy off-diagonal roles).
     // Loads and stores run for every stage, also past the chunk's end (out
     // of the buffer's range: 0, no memory access), so that every path issues
     // the same loads and each store waits for its own loads only.
-    constexpr int D = SIDES == 1 ? 6 : 2;
+    constexpr int D = SIDES == 1 ? 4 : 2;
     StageRegs<SIDES> g[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) load_stage(ln, g[j], j * kStage);
@@ -403,9 +404,11 @@ __device__ __forceinline__ int64_t xcd_local(int64_t b, int64_t total) {
 
 // One launch per pair kind, so each kernel is register-allocated for its own
 // roles: kOffPairs = false runs the ns diagonal pairs (R == C) of every
-// channel, true the ns (ns - 1) / 2 off-diagonal pairs (R < C).
+// channel, true the ns (ns - 1) / 2 off-diagonal pairs (R < C).  Diagonal
+// pairs are built for two workgroups per CU (4 waves per SIMD, 128 VGPRs,
+// 76 KB of LDS each), so one's barriers and loads overlap the other's work.
 template <bool kOffPairs>
-__global__ __launch_bounds__(kThreads, 1) void gram_kernel(Args a) {
+__global__ __launch_bounds__(kThreads, kOffPairs ? 1 : 4) void gram_kernel(Args a) {
     constexpr int SIDES = kOffPairs ? 2 : 1;
     __shared__ Lds<SIDES> L;
     const int tid = threadIdx.x;

@@ -418,9 +418,10 @@ xe_status launch_batch(xe_handle h, int slot, const SlotShape &sh, hipStream_t s
 namespace {
 
 // Work split of the flag Gram kernel: (channel, super-block pair, time
-// chunk); chunks of at least 4 stages, about one workgroup per compute unit
-// (each chunk adds its counts with atomics and reloads its pipeline, so
-// fewer, longer chunks win once every unit is busy).
+// chunk); chunks of at least 4 stages, about two workgroups per compute
+// unit (two diagonal-pair workgroups share a CU; each chunk adds its counts
+// with atomics and reloads its pipeline, so chunks stay as long as that
+// allows).
 xe::flag::Args flag_args(const uint32_t *flags, const uint8_t *mask, int32_t N, int32_t F,
                          int32_t T, int32_t B, int32_t *d, int n_cu) {
     using namespace xe::flag;
@@ -437,7 +438,7 @@ xe::flag::Args flag_args(const uint32_t *flags, const uint8_t *mask, int32_t N, 
     a.ns = (N + 255) / 256;
     const int64_t units = (int64_t)F * (a.ns * (a.ns + 1) / 2);
     const int64_t stages = (T + kStage - 1) / kStage;
-    int64_t want = ((int64_t)std::max(n_cu, 1) + units - 1) / units;
+    int64_t want = (2 * (int64_t)std::max(n_cu, 1) + units - 1) / units;
     const int64_t most = std::max<int64_t>(1, stages / 4);
     want = std::min(std::max<int64_t>(want, 1), most);
     // a chunk's validity bits fit the kernel's LDS window
