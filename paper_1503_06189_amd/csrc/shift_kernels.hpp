@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(const uint8_t *in,
                 const int64_t l = (int64_t)dk[k] - t0, u = (int64_t)T + dk[k] - t0;
                 rlo[k] = (int)(l < 0 ? 0 : (l > nt ? nt : l));
                 rhi[k] = (int)(u < 0 ? 0 : (u > nt ? nt : u));
-                base[k] = hi - dk[k];
+                base[k] = staged ? hi - dk[k] : 0;   // in [0, kSpan] when staged
             }
             for (int r = tid >> 6; r < nt; r += kTileThreads / 64) {
                 const int t = t0 + r;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(const uint8_t *in,
             const int64_t l = (int64_t)dc - t0, u = (int64_t)T + dc - t0;
             const int rlo = (int)(l < 0 ? 0 : (l > nt ? nt : l));
             const int rhi = (int)(u < 0 ? 0 : (u > nt ? nt : u));
-            const int base = hi - dc;
+            const int base = staged ? hi - dc : 0;
             // four rows per pass: their reads are in flight together
             for (int r0 = 0; r0 < nt; r0 += 4) {
                 bool set[4];
