@@ -224,7 +224,7 @@ __device__ __forceinline__ Lane<SIDES> make_lane(const Args &a, int f, int R, in
 }
 
 // stage starting ts samples into the chunk; offsets stay below 2^31 (a chunk
-// holds at most 65536 samples of at most 512 bytes)
+// holds at most 32768 samples of at most 512 bytes)
 template <int SIDES>
 __device__ __forceinline__ void load_stage(const Lane<SIDES> &l, StageRegs<SIDES> &g, int ts) {
     const uint32_t row = (uint32_t)(ts + l.smp) * l.row_bytes;

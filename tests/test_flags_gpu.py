@@ -107,6 +107,37 @@ def test_flag_counts_match_oracle(xe, orc, case):
     assert np.array_equal(got, d), np.argwhere(got != d)[:5]
 
 
+def _sparse_words(rng, F, T, N, k):
+    """[F][T][W] flag words with each bit set with probability 2^-k (the AND
+    of k random words), garbage in the padding bits, and a flag-free span."""
+    shape = (F, T, synth.flag_words(N))
+    w = rng.integers(0, 2 ** 32, shape, dtype=np.uint32)
+    for _ in range(k - 1):
+        w &= rng.integers(0, 2 ** 32, shape, dtype=np.uint32)
+    w[:, T // 3:T // 2] = 0
+    return w
+
+
+@pytest.mark.parametrize("seed,N,F,T,B,k", [(14, 32, 512, 40000, 100, 3),
+                                            (15, 290, 180, 33000, 7, 7)])
+def test_flag_counts_window_capped_chunks(xe, orc, seed, N, F, T, B, k):
+    """Frames long enough that one time chunk would pass the kernel's
+    1024-word validity window (32,768 samples), with enough channels that
+    the occupancy target alone asks for one chunk: the window cap splits
+    the frame (ragged last stage), on the diagonal kernel and, at N = 290,
+    the off-diagonal one too."""
+    rng = np.random.default_rng(seed)
+    flags = _sparse_words(rng, F, T, N, k)
+    mask = synth.bernoulli_mask(rng, F, T, B, 0.05)
+    _say(f"flag counts window cap N={N} F={F} T={T} B={B}")
+    _, d = _oracle_d(orc, flags, mask, N, B)
+    dcount = xe.new_flag_counts(N, F)
+    xe.flag_accumulate(_dev(flags), _dev(mask), B, N, dcount)
+    torch.cuda.synchronize()
+    got = dcount.cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, d), np.argwhere(got != d)[:5]
+
+
 def test_flag_counts_accumulate_over_frames(xe, orc):
     N, F, B = 300, 2, 64
     dcount = _dev(np.random.default_rng(11).integers(0, 1000, (F, N * (N + 1) // 2),
