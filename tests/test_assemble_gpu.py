@@ -148,3 +148,57 @@ def test_assemble_pathfinder_full_size(xe, orc):
     v = vis.cpu().numpy()
     assert np.array_equal(v[fs, idx].astype(np.int64), ev)
     assert np.array_equal(cnt.cpu().numpy(), orc.valid_counts(want[1], fr.F, fr.T, 4))
+
+
+def _set_seq(pk, j, seq):
+    h = pk[j, :16].view("<u8").copy()
+    h[0] = np.uint64(seq)
+    pk[j, :16] = h.view(np.uint8)
+
+
+@pytest.mark.parametrize("N", [4095, 4096])
+def test_assemble_widest_packets(xe, orc, N):
+    """The widest input count (packets of 147 KB, 128 flag words per row),
+    on the byte path (N odd) and the 16-byte path, with drops and
+    duplicates."""
+    S, T, base, seq0 = 1, 32, 2, 40
+    rng, packed, flags = _frame(200 + N, N, S, T)
+    pk = synth.packetize(packed, flags, stream_base=base, seq0=seq0)
+    pk = synth.network_faults(rng, pk, p_drop=0.25, p_dup=0.5, window=4, n_stray=1,
+                              stray_seq=seq0 + T // 4)
+    _say(f"assemble widest N={N} packets={len(pk)}")
+    _compare(_run(xe, pk, N, S, base, seq0, T), orc.assemble(pk, N, S, base, seq0, T))
+
+
+def test_assemble_sequence_limits(xe, orc):
+    """A window that starts just below 2^63, with packets one before it and
+    at the largest uint64 sequence number (both outside, counted as such)."""
+    N, S, T, base = 48, 2, 64, 0
+    seq0 = (1 << 63) - 100
+    rng, packed, flags = _frame(210, N, S, T)
+    pk = synth.packetize(packed, flags, stream_base=base, seq0=seq0)
+    pk = synth.network_faults(rng, pk, p_drop=0.1, p_dup=0.1, window=8)
+    extra = pk[:2].copy()
+    _set_seq(extra, 0, seq0 - 1)
+    _set_seq(extra, 1, (1 << 64) - 1)
+    pk = np.concatenate([extra[:1], pk, extra[1:]])
+    _say(f"assemble sequence limits packets={len(pk)}")
+    got = _run(xe, pk, N, S, base, seq0, T)
+    want = orc.assemble(pk, N, S, base, seq0, T)
+    _compare(got, want)
+    assert want[3][1] == 2
+
+
+def test_assemble_without_flags(xe, orc):
+    """Flags are optional: frame, mask and counters as with them."""
+    N, S, T, base, seq0 = 64, 2, 64, 5, 9
+    rng, packed, flags = _frame(220, N, S, T)
+    pk = synth.packetize(packed, flags, stream_base=base, seq0=seq0)
+    pk = synth.network_faults(rng, pk, p_drop=0.2, p_dup=0.2, window=8)
+    _say("assemble without flags")
+    p, m, _, st = _garbage_outputs(T, 8 * S, N)
+    xe.assemble_frame(torch.from_numpy(pk).cuda(), N, S, base, seq0, T, p, m, None, st,
+                      with_flags=False)
+    torch.cuda.synchronize()
+    want = orc.assemble(pk, N, S, base, seq0, T)
+    _compare((p.cpu().numpy(), m.cpu().numpy(), want[2], st.cpu().numpy()), want)
