@@ -89,6 +89,10 @@ SHAPES = [
     (257, 1, 200, 3, 0.2),
     (300, 1, 95, 1000, 0.0),
     (513, 1, 70, 16, 0.2),
+    # few channels over long frames: dozens of time chunks merged, counts
+    # taken by the merge
+    (64, 1, 20000, 100, 0.1),
+    (300, 2, 9001, 37, 0.1),
 ]
 
 
