@@ -41,12 +41,15 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(const uint8_t *in,
     __shared__ int32_t dl[kCols];
     __shared__ int32_t red[2][kTileThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int i_tiles = (N + kCols - 1) / kCols, t_tiles = (T + kRows - 1) / kRows;
+    // channels vary fastest: workgroups that run together read and write
+    // whole sample rows (F x N contiguous bytes) rather than 256-byte pieces
+    // a row apart
+    const int i_tiles = (N + kCols - 1) / kCols;
     int64_t b = blockIdx.x;
     const int it = (int)(b % i_tiles);
     b /= i_tiles;
-    const int tt = (int)(b % t_tiles);
-    const int f = (int)(b / t_tiles);
+    const int f = (int)(b % F);
+    const int tt = (int)(b / F);
     const int i0 = it * kCols, t0 = tt * kRows;
     const int ni = min(kCols, N - i0), nt = min(kRows, T - t0);
 
