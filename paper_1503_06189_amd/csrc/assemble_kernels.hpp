@@ -120,9 +120,11 @@ __global__ void count_kernel(const int32_t *owner, int64_t n, unsigned long long
 // kVec: 16-byte copies (N even, frame and packets 16-byte aligned)
 template <bool kVec>
 __global__ __launch_bounds__(kPlaceThreads) void place_kernel(Args a) {
+    // streams vary fastest: workgroups that run together read packets that
+    // arrived side by side and write whole sample rows of the frame
     const int64_t q = blockIdx.x;
-    const int s = (int)(q / a.slots), k = (int)(q % a.slots);
-    const int32_t p = a.owner[q];
+    const int s = (int)(q % a.n_streams), k = (int)(q / a.n_streams);
+    const int32_t p = a.owner[(int64_t)s * a.slots + k];
     const bool lost = p == kNone;
     const int F = kBands * a.n_streams;
     const uint8_t *pkt = lost ? nullptr : a.packets + (int64_t)p * a.pbytes;
