@@ -639,7 +639,7 @@ def main():
             "bound": "mfma",
             "achieved": round(achieved_tops, 2),
             "peak": MFMA_INT8_PEAK_TOPS,
-            "unit": "TFLOP/s",
+            "unit": "TOPS",
             "frac": round(achieved_tops / MFMA_INT8_PEAK_TOPS, 4),
             "traffic": measured_traffic(),
         },

@@ -4,7 +4,7 @@ Submodules:
   xengine  -- ctypes binding of libxengine.so (the HIP path)
   synth    -- seeded synthetic frames and loss masks
   metrics  -- rate and work definitions for reports
-  batch    -- batched persistent launches and the tile-shape autotuner
+  tune     -- autotuner of batched persistent launches (cached per device)
   serve    -- streaming server: admission by HBM budget, continuous batching
 """
 

@@ -84,6 +84,12 @@ struct DeviceGuard {
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// A loss block longer than the frame is one block covering all of it, as a
+// block of exactly T samples is: the mask has ceil(T/B) = 1 entry per
+// channel either way.  Kernels take the clamped length, so block indices
+// and bounds (b * B, (b + 1) * B, T + B - 1) stay far inside int32.
+int32_t eff_block(int32_t B, int32_t T) { return B < T ? B : T; }
+
 xe_status check_shape(xe_handle h, int32_t N, int32_t F, int32_t T, int32_t B) {
     if (N < 1 || N > XE_MAX_N) return fail(h, XE_ERR_ARG, "N must be in [1, 4096]");
     if (F < 1) return fail(h, XE_ERR_ARG, "F must be >= 1");
@@ -168,6 +174,7 @@ xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, i
     a.N = N;
     a.F = F;
     a.T = T;
+    B = eff_block(B, T);
     a.B = B;
     a.nblk_mask = xe::ceil_div(T, B);
     a.nb = p.blocks;
@@ -317,8 +324,8 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
         b.N = x.N;
         b.F = x.F;
         b.T = x.T;
-        b.B = x.B;
-        b.nblk_mask = xe::ceil_div(x.T, x.B);
+        b.B = eff_block(x.B, x.T);
+        b.nblk_mask = xe::ceil_div(x.T, b.B);
         b.nb = nb;
         b.groups = G;
         b.splits = splits;
@@ -629,7 +636,7 @@ xe_status xe_flag_accumulate(xe_handle h, const uint32_t *flags, const uint8_t *
     if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
-    xe::flag::Args a = flag_args(flags, loss_mask, N, F, T, B, dcount, h->n_cu);
+    xe::flag::Args a = flag_args(flags, loss_mask, N, F, T, eff_block(B, T), dcount, h->n_cu);
     const int64_t diag_blocks = (int64_t)F * a.ns * a.chunks;
     const int64_t off_blocks = (int64_t)F * (a.ns * (a.ns - 1) / 2) * a.chunks;
     hipLaunchKernelGGL(xe::flag::gram_kernel<false>, dim3((unsigned)diag_blocks),

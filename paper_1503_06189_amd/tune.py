@@ -97,6 +97,8 @@ def tune(items: Sequence[Tuple], handle: Optional[xengine.Handle] = None,
     timings = {}
     stream = torch.cuda.current_stream(dev)
     for cs in candidates(shapes, n_cu):
+        for _, _, _, v, _ in scratch:     # every candidate integrates afresh
+            xengine.reset_integration(v)
         plan = xengine.BatchPlan(scratch, chunk_steps=cs, handle=h)
         try:
             plan.run(stream)   # warm-up

@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 import threading
+import weakref
 from typing import Optional, Sequence, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -48,41 +49,79 @@ class XEngineError(RuntimeError):
         self.status = status
 
 
-# Samples integrated into each accumulator since it was last cleared, keyed by
-# the sums' device address.  int32 sums are exact for at most XE_MAX_SAMPLES
-# accumulated samples (|Re V| <= 128 per sample); calls that would pass that
-# bound are refused before launching.  correlate_frame and new_accumulators
-# start a count; callers that clear sums themselves call reset_integration.
-# Replays of a captured graph bypass this bookkeeping.
+# Samples integrated into each accumulator since it was last cleared.  int32
+# sums are exact for at most XE_MAX_SAMPLES accumulated samples (|Re V| <= 128
+# per sample); calls that would pass that bound are refused before launching,
+# and a call's samples are charged only once the library has accepted it.
+# correlate_frame and new_accumulators start a count; callers that clear sums
+# themselves call reset_integration.  Replays of a captured graph bypass this
+# bookkeeping.
+#
+# An entry is keyed by the sums' device address but holds a weak reference to
+# the tensor that owns the count: once that tensor is freed the entry is
+# stale, so a new tensor that the allocator places at the same address starts
+# from 0 instead of inheriting the old count.  A view of a live accumulator
+# (same address) shares its count.
 _integrated = {}
 _integrated_lock = threading.Lock()
+
+
+def _entry_count(key: int) -> int:
+    e = _integrated.get(key)
+    if e is None:
+        return 0
+    ref, n = e
+    t = ref()
+    if t is None or t.data_ptr() != key:
+        del _integrated[key]
+        return 0
+    return n
+
+
+def _set_count(vis, n: int) -> None:
+    key = vis.data_ptr()
+    e = _integrated.get(key)
+    if e is not None:
+        owner = e[0]()
+        if owner is not None and owner.data_ptr() == key:
+            _integrated[key] = (e[0], n)
+            return
+    _integrated[key] = (weakref.ref(vis), n)
 
 
 def reset_integration(vis) -> None:
     """Mark the sums in ``vis`` as cleared (0 samples integrated)."""
     with _integrated_lock:
-        _integrated[vis.data_ptr()] = 0
+        _set_count(vis, 0)
 
 
 def integrated_samples(vis) -> int:
     """Samples integrated into ``vis`` since it was last cleared."""
     with _integrated_lock:
-        return _integrated.get(vis.data_ptr(), 0)
+        return _entry_count(vis.data_ptr())
 
 
-def _charge(pairs) -> None:
-    """Add T samples to each (vis, T); refuse all if one would pass the bound."""
+def _charge(pairs, call):
+    """Run ``call`` (which returns an xe_status and raises on failure) only if
+    adding T samples to each (vis, T) keeps every count within the bound;
+    the counts are updated after the call succeeded."""
     with _integrated_lock:
         new = {}
+        owners = {}
         for vis, T in pairs:
             key = vis.data_ptr()
-            n = new.get(key, _integrated.get(key, 0)) + int(T)
+            n = new.get(key, _entry_count(key)) + int(T)
             if n > XE_MAX_SAMPLES:
                 raise XEngineError(XE_ERR_OVERFLOW,
                                    f"{n} samples would exceed the int32 integration bound "
                                    f"{XE_MAX_SAMPLES}; normalise and clear the sums first")
             new[key] = n
-        _integrated.update(new)
+            owners[key] = vis
+    result = call()
+    with _integrated_lock:
+        for key, n in new.items():
+            _set_count(owners[key], n)
+    return result
 
 
 class PlanInfo(ctypes.Structure):
@@ -281,7 +320,7 @@ def correlate_frame(packed, mask=None, B: int = 256, vis=None, count=None,
         N, F, T, B, ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(count.data_ptr()),
         _stream_ptr(stream)))
     with _integrated_lock:
-        _integrated[vis.data_ptr()] = T
+        _set_count(vis, T)
     return vis, count
 
 
@@ -290,13 +329,12 @@ def accumulate(packed, mask, B: int, vis, count, handle: Optional[Handle] = None
     """vis += V(frame), count += n(frame), in place on the device."""
     T, F, N = _check_frame(packed, mask, B)
     _check_acc(vis, count, N, F)
-    _charge([(vis, T)])
     h = handle or default_handle(packed.device.index)
-    h.check(lib().xe_accumulate(
+    _charge([(vis, T)], lambda: h.check(lib().xe_accumulate(
         h.ptr, ctypes.c_void_p(packed.data_ptr()),
         ctypes.c_void_p(mask.data_ptr() if mask is not None else None),
         N, F, T, B, ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(count.data_ptr()),
-        _stream_ptr(stream)))
+        _stream_ptr(stream))))
     return vis, count
 
 
@@ -496,9 +534,10 @@ def _instances(items: Sequence[Tuple]):
 def accumulate_batch(items: Sequence[Tuple], handle: Optional[Handle] = None, stream=None):
     """items: (packed, mask, B, vis, count) per instance; one persistent launch."""
     arr, dev = _instances(items)
-    _charge([(v, p.shape[0]) for p, m, B, v, c in items])
     h = handle or default_handle(dev)
-    h.check(lib().xe_accumulate_batch(h.ptr, arr, len(items), _stream_ptr(stream)))
+    _charge([(v, p.shape[0]) for p, m, B, v, c in items],
+            lambda: h.check(lib().xe_accumulate_batch(h.ptr, arr, len(items),
+                                                      _stream_ptr(stream))))
 
 
 class BatchPlan:
@@ -517,9 +556,9 @@ class BatchPlan:
         self.plan_id = pid.value
 
     def run(self, stream=None) -> None:
-        _charge([(v, p.shape[0]) for p, m, B, v, c in self.items])
-        self.handle.check(lib().xe_batch_run(self.handle.ptr, self.plan_id,
-                                             _stream_ptr(stream)))
+        _charge([(v, p.shape[0]) for p, m, B, v, c in self.items],
+                lambda: self.handle.check(lib().xe_batch_run(self.handle.ptr, self.plan_id,
+                                                             _stream_ptr(stream))))
 
     def release(self) -> None:
         if self.plan_id >= 0:

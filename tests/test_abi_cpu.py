@@ -303,16 +303,52 @@ def test_integration_bound_bookkeeping():
     """Samples integrated per accumulator are counted and a call that would
     pass the int32 bound is refused before anything is launched."""
     torch = pytest.importorskip("torch")
+    ok = lambda: 0                               # noqa: E731  (a call that succeeds)
     vis = torch.zeros(4, dtype=torch.int32)
     other = torch.zeros(4, dtype=torch.int32)
     xe.reset_integration(vis)
-    xe._charge([(vis, xe.XE_MAX_SAMPLES - 10)])
+    xe._charge([(vis, xe.XE_MAX_SAMPLES - 10)], ok)
     assert xe.integrated_samples(vis) == xe.XE_MAX_SAMPLES - 10
-    xe._charge([(vis, 10)])                      # exactly at the bound: allowed
-    with pytest.raises(xe.XEngineError) as e:
-        xe._charge([(other, 5), (vis, 1)])       # one over: the whole call is refused
+    xe._charge([(vis, 10)], ok)                  # exactly at the bound: allowed
+    ran = []
+    with pytest.raises(xe.XEngineError) as e:    # one over: the whole call is refused
+        xe._charge([(other, 5), (vis, 1)], lambda: ran.append(1))
     assert e.value.status == xe.XE_ERR_OVERFLOW
+    assert not ran                               # ... before the call was made
     assert xe.integrated_samples(other) == 0     # nothing was charged
     xe.reset_integration(vis)
-    xe._charge([(vis, 1), (vis, 2)])             # the same sums twice in one batch
+    xe._charge([(vis, 1), (vis, 2)], ok)         # the same sums twice in one batch
     assert xe.integrated_samples(vis) == 3
+
+
+def test_integration_bound_failed_call_charges_nothing():
+    """A call the library rejects adds no samples to the count."""
+    torch = pytest.importorskip("torch")
+    vis = torch.zeros(4, dtype=torch.int32)
+    xe.reset_integration(vis)
+
+    def rejected():
+        raise xe.XEngineError(xe.XE_ERR_ARG, "rejected")
+    with pytest.raises(xe.XEngineError):
+        xe._charge([(vis, 100)], rejected)
+    assert xe.integrated_samples(vis) == 0
+
+
+def test_integration_bound_not_inherited_at_a_recycled_address():
+    """The count belongs to the tensor: once it is freed, a tensor at the
+    same address starts from 0; a live view of the same sums shares it."""
+    torch = pytest.importorskip("torch")
+    import gc
+    vis = torch.zeros(64, dtype=torch.int32)
+    xe.reset_integration(vis)
+    xe._charge([(vis, 1000)], lambda: 0)
+    view = vis.view(8, 8)
+    assert xe.integrated_samples(view) == 1000   # same memory, same count
+    addr = vis.data_ptr()
+    del vis, view
+    gc.collect()
+
+    class Stand:                                 # a new tensor at the old address
+        def data_ptr(self):
+            return addr
+    assert xe.integrated_samples(Stand()) == 0

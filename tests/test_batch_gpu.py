@@ -109,26 +109,104 @@ def test_batch_with_large_n_and_unaligned(xe, orc):
     _check_oracle(orc, insts)
 
 
-def test_batch_equals_plain_launches_full_size(xe, orc):
-    """128 uneven instances at full size: the batch equals the instances'
-    own plain launches bit for bit."""
+@pytest.fixture(scope="module")
+def full_batch(orc):
+    """The 128 uneven instances at full size and the oracle's sums for each."""
     frs = synth.batched()
-    _say(f"batch vs plain launches: {len(frs)} instances, "
-         f"{sum(f.packed.size for f in frs) / 1e6:.0f} MB")
+    _say(f"oracle: {len(frs)} instances, {sum(f.packed.size for f in frs) / 1e6:.0f} MB "
+         "(about a minute)")
+    want = []
+    for k, fr in enumerate(frs):
+        want.append(orc.correlate(fr.packed, fr.mask, fr.B))
+        if k % 32 == 31:
+            _say(f"oracle: {k + 1} instances done")
+    return frs, want
+
+
+def test_batch_full_size_matches_oracle(xe, orc, full_batch):
+    """All 128 instances in one persistent launch, chunk length from the
+    autotuner's search space as the benchmark runs it, replayed from a
+    captured graph: every instance's sums equal the oracle's."""
+    frs, want = full_batch
+    insts = [Inst(xe, f) for f in frs]
+    from paper_1503_06189_amd import tune
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        cs = tune.tune([i.item() for i in insts], path=d + "/tune.json", reps=2)
+    _say(f"tuned chunk length {cs} steps")
+    for ins in insts:
+        ins.zero()
+    plan = xe.BatchPlan([i.item() for i in insts], chunk_steps=cs)
+    try:
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                plan.run()
+        torch.cuda.current_stream().wait_stream(s)
+        g.replay()
+        torch.cuda.synchronize()
+        del g
+    finally:
+        plan.release()
+    for k, (ins, (ev, en)) in enumerate(zip(insts, want)):
+        assert np.array_equal(ins.cnt.cpu().numpy(), en), f"instance {k} counts"
+        assert np.array_equal(ins.vis.cpu().numpy(), ev), f"instance {k} ({ins.fr.name}) vis"
+
+
+def test_batch_equals_plain_launches_full_size(xe, orc, full_batch):
+    """128 uneven instances at full size: the batch equals the instances'
+    own plain launches, and both equal the oracle, bit for bit."""
+    frs, want = full_batch
+    _say(f"batch vs plain launches: {len(frs)} instances")
     insts = [Inst(xe, f) for f in frs]
     for ins in insts:
         xe.accumulate(*ins.item())
     torch.cuda.synchronize()
-    want = [(i.vis.clone(), i.cnt.clone()) for i in insts]
+    plain = [(i.vis.clone(), i.cnt.clone()) for i in insts]
     for ins in insts:
         ins.zero()
     xe.accumulate_batch([i.item() for i in insts])
     torch.cuda.synchronize()
-    for k, (ins, (v, n)) in enumerate(zip(insts, want)):
+    for k, (ins, (v, n), (ev, en)) in enumerate(zip(insts, plain, want)):
         assert torch.equal(ins.cnt, n), f"instance {k} counts"
         assert torch.equal(ins.vis, v), f"instance {k} ({ins.fr.name}) vis"
-        fr = ins.fr
-        assert int(n[0].item()) == int(orc.valid_counts(fr.mask, fr.F, fr.T, fr.B)[0])
+        assert np.array_equal(v.cpu().numpy(), ev), f"instance {k} plain launch vs oracle"
+        assert np.array_equal(n.cpu().numpy(), en)
+
+
+def test_batch_deterministic_under_permuted_work_list(xe, orc):
+    """The same instances handed over in three different orders (so the
+    work list drains in a different order, with different chunks sharing
+    the GPU) and two chunk lengths: identical sums every time."""
+    frs = _frames(32, 0.1, (64, 128, 256, 512), seed=synth.SEEDS["batched"] + 7)
+    insts = [Inst(xe, f) for f in frs]
+    rng = np.random.default_rng(3)
+    ref = None
+    for trial, cs in enumerate((0, 0, 0, 64)):
+        order = rng.permutation(len(insts)) if trial else np.arange(len(insts))
+        for ins in insts:
+            ins.zero()
+        xe.accumulate_batch([insts[k].item() for k in order], )
+        if cs:
+            for ins in insts:
+                ins.zero()
+            plan = xe.BatchPlan([insts[k].item() for k in order], chunk_steps=cs)
+            try:
+                plan.run()
+            finally:
+                torch.cuda.synchronize()
+                plan.release()
+        torch.cuda.synchronize()
+        got = [(i.vis.cpu().numpy(), i.cnt.cpu().numpy()) for i in insts]
+        if ref is None:
+            ref = got
+            _check_oracle(orc, insts)
+        else:
+            for k, ((v, n), (rv, rn)) in enumerate(zip(got, ref)):
+                assert np.array_equal(v, rv) and np.array_equal(n, rn), \
+                    f"trial {trial}: instance {k} differs"
 
 
 def test_batch_ring_reuse(xe, orc):

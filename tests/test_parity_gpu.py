@@ -1,8 +1,11 @@
 """HIP path vs the oracle, element by element (GPU).
 
-Integer visibilities and counts must be bit-exact; normalised float32 must
-stay within 1e-6 relative of the oracle's FP64 normalisation (both divide in
-double and round once, so in practice they are identical).
+Integer visibilities and counts must be bit-exact.  The stated tolerance of
+the normalised float32 output is 1e-6 relative to the oracle's FP64
+normalisation; both sides divide the same integers in double and round once
+to float32, so the tests require the float32 values to be identical, which
+implies that tolerance.  The full-size workloads are compared over their
+whole output, in the launch configuration the benchmark times.
 """
 
 import sys
@@ -53,16 +56,24 @@ def run_gpu(xe, fr, normalize=False):
     return res
 
 
-def check_full(xe, orc, fr, normalize=True):
+def assert_same_floats(got, want):
+    """float32 outputs identical bit for bit (within 1e-6 relative a fortiori)."""
+    assert got.dtype == np.float32 and want.dtype == np.float32
+    assert got.shape == want.shape
+    bad = np.argwhere(got.view(np.uint32) != want.view(np.uint32))
+    assert bad.size == 0, f"{len(bad)} normalised values differ, first {bad[:5].tolist()}"
+    np.testing.assert_allclose(got, want, rtol=1e-6, atol=0)
+
+
+def check_full(xe, orc, fr, normalize=True, expect=None):
     _say(f"case {fr.name} N={fr.N} F={fr.F} T={fr.T} B={fr.B} seed={fr.seed}")
     got = run_gpu(xe, fr, normalize)
-    ev, en = orc.correlate(fr.packed, fr.mask, fr.B)
+    ev, en = expect if expect is not None else orc.correlate(fr.packed, fr.mask, fr.B)
     assert np.array_equal(got[1], en), "counts differ"
     bad = np.argwhere(got[0] != ev)
     assert bad.size == 0, f"{len(bad)} visibilities differ, first {bad[:5].tolist()}"
     if normalize:
-        eo = orc.normalize(ev, en)
-        np.testing.assert_allclose(got[2], eo, rtol=1e-6, atol=0)
+        assert_same_floats(got[2], orc.normalize(ev, en))
 
 
 # ---------------------------------------------------------------------------
@@ -185,19 +196,72 @@ def check_sampled(xe, orc, fr, n_pairs=3000):
     np.testing.assert_allclose(out[fs, idx], eo[:, 0, :], rtol=1e-6, atol=0)
 
 
-def test_pathfinder_full_size(xe, orc):
-    """N=256, 64 channels, 16384 samples, 1% block loss: the bench workload."""
+@pytest.fixture(scope="module")
+def pathfinder(orc):
+    fr = synth.pathfinder()
+    _say(f"oracle: {fr.name} N={fr.N} F={fr.F} T={fr.T} (whole frame)")
+    return fr, orc.correlate(fr.packed, fr.mask, fr.B)
+
+
+def test_pathfinder_full_size(xe, orc, pathfinder):
+    """N=256, 64 channels, 16384 samples, 1% block loss (the bench workload):
+    every visibility, count and normalised value of the frame."""
+    fr, expect = pathfinder
+    check_full(xe, orc, fr, expect=expect)
+
+
+def test_pathfinder_accumulate_as_benched(xe, orc, pathfinder):
+    """The benchmark's call: xe_accumulate into resident sums (its time-
+    chunked launch and merge), three frames, then xe_normalize; the whole
+    integration equals three times the oracle's frame."""
+    fr, (ev, en) = pathfinder
+    _say(f"case {fr.name} accumulate x3 (whole frame)")
+    plan = xe.plan_query(fr.N, fr.F, fr.T, fr.B)
+    assert plan.splits > 1    # the chunked path with its merge kernel
+    packed, mask = _dev(fr.packed), _dev(fr.mask)
+    vis, cnt = xe.new_accumulators(fr.N, fr.F, packed.device)
+    for _ in range(3):
+        xe.accumulate(packed, mask, fr.B, vis, cnt)
+    out = xe.normalize(vis, cnt)
+    torch.cuda.synchronize()
+    assert np.array_equal(cnt.cpu().numpy(), 3 * en)
+    got = vis.cpu().numpy()
+    bad = np.argwhere(got != 3 * ev)
+    assert bad.size == 0, f"{len(bad)} visibilities differ, first {bad[:5].tolist()}"
+    assert_same_floats(out.cpu().numpy(), orc.normalize(3 * ev, 3 * en))
+
+
+def test_pathfinder_sampled_pairs(xe, orc):
+    """Sampled baselines through the oracle's per-pair routine and the
+    autocorrelation properties, on the same frame."""
     check_sampled(xe, orc, synth.pathfinder())
 
 
 def test_large_n_full_size(xe, orc):
-    """N=2048, 16 channels, 8192 samples, 0.5% loss."""
+    """N=2048, 16 channels, 8192 samples, 0.5% loss: the whole output
+    (2,098,176 baselines per channel)."""
+    fr = synth.large_n()
+    _say(f"oracle: {fr.name} N={fr.N} F={fr.F} T={fr.T} (whole frame, about a minute)")
+    check_full(xe, orc, fr)
+
+
+def test_large_n_sampled_pairs(xe, orc):
     check_sampled(xe, orc, synth.large_n(), n_pairs=2000)
 
 
 def test_max_n(xe, orc):
+    """N=4096 (the largest a call takes), whole output."""
     fr = synth.random_bytes_frame(4096, 4096, 1, 40, 16, p_loss=0.2)
-    check_sampled(xe, orc, fr, n_pairs=2000)
+    check_full(xe, orc, fr)
+
+
+def test_block_longer_than_frame(xe, orc):
+    """A loss block longer than the frame (up to INT32_MAX samples) is one
+    block covering it: its single mask entry decides every sample."""
+    for B in (301, 1 << 20, 2**31 - 1):
+        fr = synth.random_bytes_frame(31, 40, 3, 300, B, p_loss=0.0, fill="garbage")
+        fr.mask = np.array([[0], [1], [0]], dtype=np.uint8)
+        check_full(xe, orc, fr)
 
 
 def test_overflow_edge(xe):
@@ -232,7 +296,7 @@ def test_integration_bound_refused(xe):
     xe.accumulate(packed, None, fr.B, vis, cnt)
     torch.cuda.synchronize()
     before = vis.clone()
-    xe._charge([(vis, xe.XE_MAX_SAMPLES - fr.T - 1)])
+    xe._charge([(vis, xe.XE_MAX_SAMPLES - fr.T - 1)], lambda: 0)
     with pytest.raises(xe.XEngineError) as e:
         xe.accumulate(packed, None, fr.B, vis, cnt)
     assert e.value.status == xe.XE_ERR_OVERFLOW

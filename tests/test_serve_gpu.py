@@ -81,7 +81,38 @@ def test_mix_equals_alone_and_oracle(srv, orc, specs, pool):
             ev, en, eo = _expected(orc, s, pool, mix.sequence[s.stream_id], idx)
             assert np.array_equal(c, en), f"stream {s.stream_id} integration {idx} counts"
             assert np.array_equal(v.astype(np.int64), ev), f"stream {s.stream_id} vis"
-            np.testing.assert_allclose(o, eo, rtol=1e-6, atol=0)
+            assert np.array_equal(o.view(np.uint32), eo.view(np.uint32))
+
+
+def test_streaming_shapes_mix_equals_alone_and_oracle(srv, orc):
+    """Streams of the serving workload's shapes (N 128, 256 and 512; 16 to
+    64 channels; 4096-sample frames; bursty loss up to 10% per frame), one
+    whole integration of distinct frames each: every result in the mix
+    equals the result alone and the oracle, bit for bit."""
+    from paper_1503_06189_amd.synth import StreamSpec, stream_frame
+    base = synth.SEEDS["streaming"] * 1000 + 500
+    specs = [StreamSpec(0, 128, 64, 4096, 3, 0.05, 6.4e9, base + 0),
+             StreamSpec(1, 256, 16, 4096, 3, 0.03, 6.4e9, base + 1),
+             StreamSpec(2, 512, 24, 4096, 3, 0.05, 6.4e9, base + 2)]
+    pool = {s.stream_id: [stream_frame(s, k, 256) for k in range(3)] for s in specs}
+    _say("streaming shapes: " + " ".join(f"N={s.N},F={s.F}" for s in specs))
+    mix = srv.run_load(specs, integrations=1, distinct=3, speed=float("inf"), pool=pool)
+    assert mix.stats["mean_batch"] > 1.0
+    got_mix = _by_stream(mix)
+    for s in specs:
+        assert mix.sequence[s.stream_id] == [0, 1, 2]    # three distinct frames
+        alone = _by_stream(srv.run_load([s], integrations=1, distinct=3,
+                                        speed=float("inf"), pool=pool))[s.stream_id]
+        ((ia, va, ca, oa),) = alone
+        ((im, vm, cm, om),) = got_mix[s.stream_id]
+        assert ia == im == 0
+        assert np.array_equal(va, vm) and np.array_equal(ca, cm)
+        assert np.array_equal(oa.view(np.uint32), om.view(np.uint32))
+        ev, en, eo = _expected(orc, s, pool, mix.sequence[s.stream_id], 0)
+        assert np.array_equal(cm, en), f"stream {s.stream_id} counts"
+        assert np.array_equal(vm.astype(np.int64), ev), f"stream {s.stream_id} vis"
+        assert np.array_equal(om.view(np.uint32), eo.view(np.uint32)), \
+            f"stream {s.stream_id} normalised"
 
 
 def test_tight_budget_delays_but_does_not_change(srv, specs, pool):
