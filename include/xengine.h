@@ -276,6 +276,29 @@ typedef struct {
 xe_status xe_plan_query(int32_t N, int32_t F, int32_t T, int32_t B,
                         int32_t n_cu, xe_plan_info *info);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * computation as xe_accumulate (ADD the frame's sums into vis and count,
+ * same arguments and limits), on the current HIP device, without a handle:
+ * nothing here calls hipMalloc, hipFree or any allocating routine.
+ *
+ * The partial sums of time chunks live in one static device array of
+ * XE_NOALLOC_SCRATCH_BYTES per device, loaded with the library's code
+ * object and held until the process ends; its address is looked up on the
+ * first call on each device.  Nothing in it needs clearing between calls
+ * (every chunk overwrites its own partials before they are read).  Every
+ * call on a device shares that device's array, so calls that overlap on
+ * one GPU (different streams, or other host threads) race: serialise them
+ * on one stream.  A frame is planned into fewer time chunks when the usual
+ * plan would not fit the array; a frame whose fewest possible chunks still
+ * do not fit is rejected with XE_ERR_WORKSPACE before anything is touched.
+ * Errors: as xe_accumulate; XE_ERR_HIP when no device is current;
+ * XE_ERR_UNSUPPORTED when it is not gfx950. */
+#define XE_NOALLOC_SCRATCH_BYTES (64u << 20)
+xe_status xe_accumulate_noalloc(const uint8_t *packed, const uint8_t *loss_mask,
+                                int32_t N, int32_t F, int32_t T, int32_t B,
+                                int32_t *vis, int64_t *count, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

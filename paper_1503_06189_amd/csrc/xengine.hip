@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -159,18 +160,27 @@ bool fill_plan(int32_t N, int32_t F, int32_t T, int32_t n_cu, size_t ws_bytes,
     return splits == 1 || partial_bytes(keys, splits) <= ws_bytes;
 }
 
-xe_status launch_corr(xe_handle h, const uint8_t *packed, const uint8_t *mask, int32_t N,
-                      int32_t F, int32_t T, int32_t B, int32_t *vis, int64_t *count,
+// Where a correlation call keeps the partial sums of its time chunks: the
+// handle's workspace, or the static scratch array of the allocation-free
+// entry point.  `h` (may be null) receives the error text.
+struct Scratch {
+    void *ptr;
+    size_t bytes;
+    int n_cu;
+};
+
+xe_status launch_corr(xe_handle h, const Scratch &ws, const uint8_t *packed, const uint8_t *mask,
+                      int32_t N, int32_t F, int32_t T, int32_t B, int32_t *vis, int64_t *count,
                       bool overwrite, hipStream_t stream) {
     xe_plan_info p;
-    if (!fill_plan(N, F, T, h->n_cu, h->workspace_bytes, &p))
+    if (!fill_plan(N, F, T, ws.n_cu, ws.bytes, &p))
         return fail(h, XE_ERR_WORKSPACE, "time chunks do not fit the workspace");
     xe::CorrArgs a;
     a.packed = packed;
     a.mask = mask;
     a.vis = vis;
     a.count = count;
-    a.partials = (int32_t *)h->workspace;
+    a.partials = (int32_t *)ws.ptr;
     a.N = N;
     a.F = F;
     a.T = T;
@@ -581,8 +591,8 @@ xe_status xe_accumulate(xe_handle h, const uint8_t *packed, const uint8_t *loss_
     if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
-    return launch_corr(h, packed, loss_mask, N, F, T, B, vis, count, false,
-                       (hipStream_t)stream);
+    return launch_corr(h, Scratch{h->workspace, h->workspace_bytes, h->n_cu}, packed, loss_mask,
+                       N, F, T, B, vis, count, false, (hipStream_t)stream);
 }
 
 xe_status xe_correlate_frame(xe_handle h, const uint8_t *packed, const uint8_t *loss_mask,
@@ -593,8 +603,8 @@ xe_status xe_correlate_frame(xe_handle h, const uint8_t *packed, const uint8_t *
     if (h->device == XE_DEVICE_NONE) return XE_ERR_NO_DEVICE;
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
-    return launch_corr(h, packed, loss_mask, N, F, T, B, vis, count, true,
-                       (hipStream_t)stream);
+    return launch_corr(h, Scratch{h->workspace, h->workspace_bytes, h->n_cu}, packed, loss_mask,
+                       N, F, T, B, vis, count, true, (hipStream_t)stream);
 }
 
 xe_status xe_normalize(xe_handle h, const int32_t *vis, const int64_t *count, int32_t N,
@@ -834,7 +844,8 @@ xe_status xe_accumulate_batch(xe_handle h, const xe_instance *inst, int32_t n_in
         if (e != hipSuccess) return hip_fail(h, e, "batch ring record");
     }
     for (const xe_instance &x : plan.unaligned) {
-        s = launch_corr(h, x.packed, x.loss_mask, x.N, x.F, x.T, x.B, x.vis, x.count, false, st);
+        s = launch_corr(h, Scratch{h->workspace, h->workspace_bytes, h->n_cu}, x.packed,
+                        x.loss_mask, x.N, x.F, x.T, x.B, x.vis, x.count, false, st);
         if (s != XE_OK) return s;
     }
     return XE_OK;
@@ -882,7 +893,8 @@ xe_status xe_batch_run(xe_handle h, int32_t plan_id, void *stream) {
     xe_status s = launch_batch(h, plan_id, ps.shape, st);
     if (s != XE_OK) return s;
     for (const xe_instance &x : ps.unaligned) {
-        s = launch_corr(h, x.packed, x.loss_mask, x.N, x.F, x.T, x.B, x.vis, x.count, false, st);
+        s = launch_corr(h, Scratch{h->workspace, h->workspace_bytes, h->n_cu}, x.packed,
+                        x.loss_mask, x.N, x.F, x.T, x.B, x.vis, x.count, false, st);
         if (s != XE_OK) return s;
     }
     return XE_OK;
@@ -913,3 +925,78 @@ xe_status xe_batch_query(const xe_instance *inst, int32_t n_inst, int32_t n_cu,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// the allocation-free accumulate
+// ---------------------------------------------------------------------------
+
+// Partial sums of time chunks for xe_accumulate_noalloc: one static array
+// per device, loaded with the code object and held until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host its name
+// is a stand-in, not a device address): the address comes from
+// hipGetSymbolAddress, once per device, and is kept in g_scratch.
+static __device__ __align__(256) int32_t scratch[XE_NOALLOC_SCRATCH_BYTES / sizeof(int32_t)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct DeviceScratch {
+    bool ready = false;
+    void *ptr = nullptr;
+    int n_cu = 0;
+};
+
+std::mutex g_scratch_lock;
+DeviceScratch g_scratch[kMaxDevices];
+
+// Address and CU count of the current device's scratch array, taken on the
+// first call on that device (with the device current).
+xe_status device_scratch(Scratch *out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return XE_ERR_HIP;
+    if (dev >= kMaxDevices) return XE_ERR_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_lock);
+    DeviceScratch &d = g_scratch[dev];
+    if (!d.ready) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return XE_ERR_HIP;
+        if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return XE_ERR_UNSUPPORTED;
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+            return XE_ERR_HIP;
+        d.ptr = p;
+        d.n_cu = prop.multiProcessorCount;
+        d.ready = true;
+    }
+    *out = Scratch{d.ptr, (size_t)XE_NOALLOC_SCRATCH_BYTES, d.n_cu};
+    return XE_OK;
+}
+
+}  // namespace
+
+extern "C" xe_status xe_accumulate_noalloc(const uint8_t *packed, const uint8_t *loss_mask,
+                                           int32_t N, int32_t F, int32_t T, int32_t B,
+                                           int32_t *vis, int64_t *count, void *stream) {
+    xe_status s = check_shape(nullptr, N, F, T, B);
+    if (s != XE_OK) return s;
+    if (!packed || !vis || !count) return XE_ERR_ARG;
+    if (!aligned(vis, 8) || !aligned(count, 8)) return XE_ERR_ALIGN;
+    // Sizes beyond the scratch array: even the fewest time chunks the
+    // frame's byte offsets allow leave more partial sums than it holds.
+    // Decided on the host before any device call.
+    {
+        const int nb = xe::ceil_div(N, xe::kBlk);
+        const int64_t keys = (int64_t)F * xe::groups_per_channel(nb);
+        const int steps = xe::ceil_div(T, xe::kStep);
+        const int64_t max_sps = xe::max_steps_per_chunk(F, N);
+        const int fewest = (int)((steps + max_sps - 1) / max_sps);
+        if (partial_bytes(keys, fewest) > (size_t)XE_NOALLOC_SCRATCH_BYTES)
+            return XE_ERR_WORKSPACE;
+    }
+    Scratch ws;
+    s = device_scratch(&ws);
+    if (s != XE_OK) return s;
+    return launch_corr(nullptr, ws, packed, loss_mask, N, F, T, B, vis, count, false,
+                       (hipStream_t)stream);
+}

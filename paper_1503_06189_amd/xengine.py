@@ -36,7 +36,7 @@ EXPORTS = ("xe_create", "xe_destroy", "xe_status_string", "xe_last_error",
            "xe_accumulate_batch", "xe_batch_plan", "xe_batch_run", "xe_batch_release",
            "xe_batch_query", "xe_plan_query",
            "xe_flag_accumulate", "xe_apply_flags", "xe_normalize_flagged",
-           "xe_assemble_frame", "xe_time_shift")
+           "xe_assemble_frame", "xe_time_shift", "xe_accumulate_noalloc")
 
 
 class XEngineUnavailable(RuntimeError):
@@ -172,6 +172,8 @@ def lib() -> ctypes.CDLL:
                 fn = getattr(L, name)
                 fn.restype = i32
                 fn.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp, vp]
+            L.xe_accumulate_noalloc.restype = i32
+            L.xe_accumulate_noalloc.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp]
             L.xe_normalize.restype = i32
             L.xe_normalize.argtypes = [vp, vp, vp, i32, i32, vp, vp]
             L.xe_flag_accumulate.restype = i32
@@ -335,6 +337,28 @@ def accumulate(packed, mask, B: int, vis, count, handle: Optional[Handle] = None
         ctypes.c_void_p(mask.data_ptr() if mask is not None else None),
         N, F, T, B, ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(count.data_ptr()),
         _stream_ptr(stream))))
+    return vis, count
+
+
+def accumulate_noalloc(packed, mask, B: int, vis, count, stream=None):
+    """As :func:`accumulate`, through xe_accumulate_noalloc: no handle, no
+    device allocation (time-chunk sums in the library's static scratch
+    array of the current device).  Calls overlapping on one GPU race."""
+    import torch
+    T, F, N = _check_frame(packed, mask, B)
+    _check_acc(vis, count, N, F)
+    if torch.cuda.current_device() != packed.device.index:
+        raise ValueError("the frame must be on the current device")
+
+    def call():
+        s = lib().xe_accumulate_noalloc(
+            ctypes.c_void_p(packed.data_ptr()),
+            ctypes.c_void_p(mask.data_ptr() if mask is not None else None),
+            N, F, T, B, ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(count.data_ptr()),
+            _stream_ptr(stream))
+        if s != XE_OK:
+            raise XEngineError(s, status_string(s))
+    _charge([(vis, T)], call)
     return vis, count
 
 

@@ -352,3 +352,27 @@ def test_integration_bound_not_inherited_at_a_recycled_address():
         def data_ptr(self):
             return addr
     assert xe.integrated_samples(Stand()) == 0
+
+
+def test_noalloc_rejects_frames_beyond_its_scratch():
+    """xe_accumulate_noalloc refuses, on the host and before any device
+    call, a frame whose fewest possible time chunks need more partial sums
+    than its static array holds; argument errors come first.  (No device
+    here: an acceptable frame then fails at the device lookup.)"""
+    L = xe.lib()
+    vp = ctypes.c_void_p
+    fake = vp(0x10000000)
+
+    def call(N, F, T, B=256, packed=fake, vis=fake, count=fake):
+        return L.xe_accumulate_noalloc(packed, None, N, F, T, B, vis, count, None)
+
+    # 16 channels of 256 inputs over 8M samples: at most 16,376 steps per
+    # chunk, so at least 17 chunks, 16 x 16 x 327,680 B > 64 MiB
+    assert call(256, 16, 8 << 20) == xe.XE_ERR_WORKSPACE
+    assert call(256, 16, 100, packed=None) == xe.XE_ERR_ARG
+    assert call(0, 16, 100) == xe.XE_ERR_ARG
+    assert call(256, 16, xe.XE_MAX_SAMPLES + 1) == xe.XE_ERR_OVERFLOW
+    assert call(256, 16, 100, vis=vp(0x10000004)) == xe.XE_ERR_ALIGN
+    import torch
+    if not torch.cuda.is_available():
+        assert call(256, 16, 1000) in (xe.XE_ERR_HIP, xe.XE_ERR_UNSUPPORTED)
