@@ -68,9 +68,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if
-    they were taken on the current kernel source; else None."""
+def _pmc():
+    """The committed rocprofv3 counter summary of the correlation call, if
+    it was taken on the current kernel source; else None."""
     try:
         with open(PMC_FILE) as f:
             pmc = json.load(f)
@@ -78,11 +78,62 @@ def measured_traffic():
         return None
     if pmc.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return pmc.get("hbm_bytes_per_launch")
+    return pmc
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter runs, or None."""
+    pmc = _pmc()
+    return None if pmc is None else pmc.get("hbm_bytes_per_launch")
+
+
+def measured_execution():
+    """Executed matrix-core work of corr_kernel from the committed SQ
+    counter runs, or None: executed int8 ops against the algorithmic ones,
+    and the fraction of the kernel's cycles the SIMDs' matrix cores were
+    busy (SQ_VALU_MFMA_BUSY_CYCLES per SIMD over GRBM_GUI_ACTIVE per XCD),
+    mean over the profiled dispatches and for the fastest one."""
+    pmc = _pmc()
+    sq = None if pmc is None else pmc.get("sq")
+    if not sq:
+        return None
+    return {
+        "executed_int8_ops": sq["executed_int8_ops"],
+        "algorithmic_int8_ops": sq["algorithmic_int8_ops"],
+        "mfma_busy_frac_mean": sq["mfma_busy_frac_mean"],
+        "mfma_busy_frac_best": sq["mfma_busy_frac_best"],
+        "source": os.path.basename(PMC_FILE),
+    }
+
+
+def _single_thread_oracle(fr, n_ch: int):
+    """The oracle on n_ch channels of the frame in a child process limited
+    to one OpenMP thread; seconds of the median of 3 runs."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    with tempfile.TemporaryDirectory() as d:
+        pk = os.path.join(d, "packed.npy")
+        mk = os.path.join(d, "mask.npy")
+        np.save(pk, np.ascontiguousarray(fr.packed[:, :n_ch, :]))
+        np.save(mk, np.ascontiguousarray(fr.mask[:n_ch]))
+        code = ("import sys, time, numpy as np; sys.path.insert(0, %r); import oracle; "
+                "orc = oracle.load(); p = np.load(%r); m = np.load(%r); ts = []\n"
+                "for _ in range(3):\n"
+                "    t0 = time.perf_counter(); orc.correlate(p, m, %d); "
+                "ts.append(time.perf_counter() - t0)\n"
+                "print(sorted(ts)[1])" % (ROOT, pk, mk, fr.B))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                           text=True, timeout=600)
+        if r.returncode != 0:
+            return None
+        return float(r.stdout.strip().splitlines()[-1])
 
 
 def cpu_baseline(fr, target_s: float):
-    """Time the oracle on a prefix of channels of the frame."""
+    """Time the oracle on a prefix of channels of the frame: all host cores
+    (median of 3 runs), and one core on a smaller prefix."""
     import numpy as np
     import oracle
     from paper_1503_06189_amd import metrics
@@ -95,20 +146,33 @@ def cpu_baseline(fr, target_s: float):
     t0 = time.perf_counter()
     orc.correlate(sub, None, fr.B)
     per_sample_ch = (time.perf_counter() - t0) / t_pre
-    n_ch = max(1, min(fr.F, int(target_s / max(per_sample_ch * fr.T, 1e-9))))
+    # three runs share the time budget
+    n_ch = max(1, min(fr.F, int(target_s / 3 / max(per_sample_ch * fr.T, 1e-9))))
     sub = np.ascontiguousarray(fr.packed[:, :n_ch, :])
     mask = np.ascontiguousarray(fr.mask[:n_ch]) if fr.mask is not None else None
-    t0 = time.perf_counter()
-    orc.correlate(sub, mask, fr.B)
-    dt = time.perf_counter() - t0
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        orc.correlate(sub, mask, fr.B)
+        runs.append(time.perf_counter() - t0)
+    dt = sorted(runs)[1]
+    # one core: about 10 s of work at the calibrated multi-core rate
+    n1 = max(1, min(fr.F, int(10.0 / 3 / max(per_sample_ch * fr.T * threads, 1e-9))))
+    dt1 = _single_thread_oracle(fr, n1)
     return {
         "value": round(metrics.input_gbps(fr.N, n_ch, fr.T, dt), 6),
         "unit": "Gb/s",
         "cores": threads,
         "cpu": _cpu_model(),
         "kind": "oracle",
-        "sample": f"{n_ch} of {fr.F} channels, full {fr.T} samples, N={fr.N} "
-                  f"({dt:.1f} s of CPU work)",
+        "sample": f"{n_ch} of {fr.F} channels, full {fr.T} samples, N={fr.N}, median of 3 "
+                  f"runs ({dt:.1f} s each)",
+        "runs_s": [round(x, 3) for x in runs],
+        "single_core": None if dt1 is None else {
+            "value": round(metrics.input_gbps(fr.N, n1, fr.T, dt1), 6), "unit": "Gb/s",
+            "cores": 1,
+            "sample": f"{n1} of {fr.F} channels, full {fr.T} samples, median of 3 runs "
+                      f"({dt1:.1f} s each)"},
         "next_paths": cpu_baseline_next(orc, fr),
     }
 
@@ -642,6 +706,7 @@ def main():
             "unit": "TOPS",
             "frac": round(achieved_tops / MFMA_INT8_PEAK_TOPS, 4),
             "traffic": measured_traffic(),
+            "executed": measured_execution(),
         },
         "kernel_ms": round(kern_ms, 5),
         "kernel_alg_hbm_gbps": round(alg_bytes / (kern_ms / 1e3) / 1e9, 1),

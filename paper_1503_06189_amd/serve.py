@@ -13,7 +13,13 @@ buffers of Sec. II-A).  The server
 * keeps each stream's integration resident on the device, adding frame
   after frame (Sec. II-B), and at the end of an integration normalises it
   for lost samples (Sec. II-C) and copies it out, while the stream's next
-  integration proceeds in a second accumulator.
+  integration proceeds in a second accumulator;
+* with aligned streams, bounds every integration by the frames' sequence
+  numbers (window k holds frames k L .. k L + L - 1), so the integrations
+  of different streams cover the same time and :class:`Combiner` can join
+  them, ordered by stream id, into one output over all their channels
+  (Sec. II-C: the eight streams of a host are combined; Sec. II-D: the
+  sequence number aligns frames in time).
 
 Every compute step runs in the library's kernels (xengine); this module
 only schedules them and owns the memory accounting.  Frame latency is
@@ -43,12 +49,17 @@ class StreamConfig:
     T: int                       # samples per frame
     B: int                       # samples per loss-mask block
     frames_per_integration: int
+    # integrations bounded by sequence number: window k = frames with
+    # seq // frames_per_integration == k (a window may hold fewer frames
+    # when some never arrived); False: every frames_per_integration
+    # frames in arrival order
+    aligned: bool = False
 
 
 @dataclasses.dataclass
 class Frame:
     stream_id: int
-    seq: int
+    seq: int                     # sequence number of the frame in its stream
     packed: "object"             # pinned uint8 [T][F][N] host tensor
     mask: "object"               # pinned uint8 [F][nblk] host tensor or None
     t_arrival: float             # time.perf_counter() at arrival
@@ -69,6 +80,9 @@ class IntegrationResult:
     count: np.ndarray            # int64 [F]
     out: np.ndarray              # float32 [F][P][2]
     t_ready: float
+    seq_first: int = -1          # sequence numbers of the first and last frame
+    seq_last: int = -1
+    window: int = -1             # aligned streams: the sequence-number window
 
 
 class _Stream:
@@ -88,6 +102,9 @@ class _Stream:
         self.host_busy = [False, False]  # host copy k not yet taken
         self.cur = 0
         self.frames_in = 0           # frames launched into the current integration
+        self.seq_first = -1          # ... and the sequence numbers they span
+        self.seq_last = -1
+        self.window = -1             # aligned: window of the current integration
         self.index = 0
         self.pending: Deque[Frame] = collections.deque()   # admitted, not launched
         self.waiting: Deque[Frame] = collections.deque()   # arrived, not admitted
@@ -230,6 +247,13 @@ class StreamServer:
         cs = self.compute_stream
         items = []
         for s, fr in batch:
+            if s.cfg.aligned:
+                w = fr.seq // s.cfg.frames_per_integration
+                if s.frames_in and w != s.window:
+                    # a frame of a later window: the current one is over,
+                    # short of the frames that never came
+                    self._finish(s)
+                s.window = w
             if fr.ev_copied is not None:
                 cs.wait_event(fr.ev_copied)
             # the device tensors were made on the copy stream: keep their
@@ -245,47 +269,69 @@ class StreamServer:
         self.inflight.append((ev, [fr for _, fr in batch]))
         self.batches += 1
         self.batch_sizes.append(len(batch))
-        # integrations that this batch completes: normalise, copy out, and
-        # switch the stream to its other accumulator
+        # integrations that this batch completes
         for s, fr in batch:
+            if s.frames_in == 0:
+                s.seq_first = fr.seq
+            s.seq_last = fr.seq
             s.frames_in += 1
-            if s.frames_in < s.cfg.frames_per_integration:
-                continue
-            k = s.cur
-            vis, cnt = s.acc[k]
-            xengine.normalize(vis, cnt, s.out[k], handle=self.h, stream=cs)
-            ev_norm = torch.cuda.Event()
-            ev_norm.record(cs)
-            # the host copy of buffer k (two integrations ago) must have
-            # been taken: its copy-out is long done, collect it
-            if s.host_busy[k]:
-                s.ev_d2h[k].synchronize()
-                self._complete()
-            assert not s.host_busy[k]
-            s.host_busy[k] = True
-            hv, hc, ho = s.host[k]
-            self.d2h_stream.wait_event(ev_norm)
-            with torch.cuda.stream(self.d2h_stream):
-                hv.copy_(vis, non_blocking=True)
-                hc.copy_(cnt, non_blocking=True)
-                ho.copy_(s.out[k], non_blocking=True)
-                ev_d2h = torch.cuda.Event(enable_timing=True)
-                ev_d2h.record(self.d2h_stream)
-            s.ev_d2h[k] = ev_d2h
-            self.outgoing.append((ev_d2h, s, k, s.index, s.frames_in))
-            s.index += 1
-            s.frames_in = 0
-            s.cur ^= 1
-            nk = s.cur
-            # the other accumulator starts from zero once its last copy-out
-            # has read it
-            if s.ev_d2h[nk] is not None:
-                cs.wait_event(s.ev_d2h[nk])
-            with torch.cuda.stream(cs):
-                s.acc[nk][0].zero_()
-                s.acc[nk][1].zero_()
-                xengine.reset_integration(s.acc[nk][0])
+            L = s.cfg.frames_per_integration
+            if s.cfg.aligned:
+                if (fr.seq + 1) % L == 0:      # the window's last frame
+                    self._finish(s)
+            elif s.frames_in >= L:
+                self._finish(s)
         return True
+
+    def _finish(self, s: _Stream) -> None:
+        """End stream s's integration: normalise it, copy it out, and switch
+        the stream to its other accumulator (all on the compute stream)."""
+        torch = self.torch
+        cs = self.compute_stream
+        k = s.cur
+        vis, cnt = s.acc[k]
+        xengine.normalize(vis, cnt, s.out[k], handle=self.h, stream=cs)
+        ev_norm = torch.cuda.Event()
+        ev_norm.record(cs)
+        # the host copy of buffer k (two integrations ago) must have been
+        # taken: its copy-out is long done, collect it
+        if s.host_busy[k]:
+            s.ev_d2h[k].synchronize()
+            self._complete()
+        assert not s.host_busy[k]
+        s.host_busy[k] = True
+        hv, hc, ho = s.host[k]
+        self.d2h_stream.wait_event(ev_norm)
+        with torch.cuda.stream(self.d2h_stream):
+            hv.copy_(vis, non_blocking=True)
+            hc.copy_(cnt, non_blocking=True)
+            ho.copy_(s.out[k], non_blocking=True)
+            ev_d2h = torch.cuda.Event(enable_timing=True)
+            ev_d2h.record(self.d2h_stream)
+        s.ev_d2h[k] = ev_d2h
+        self.outgoing.append((ev_d2h, s, k, s.index, s.frames_in,
+                              (s.seq_first, s.seq_last, s.window if s.cfg.aligned else -1)))
+        s.index += 1
+        s.frames_in = 0
+        s.cur ^= 1
+        nk = s.cur
+        # the other accumulator starts from zero once its last copy-out has
+        # read it
+        if s.ev_d2h[nk] is not None:
+            cs.wait_event(s.ev_d2h[nk])
+        with torch.cuda.stream(cs):
+            s.acc[nk][0].zero_()
+            s.acc[nk][1].zero_()
+            xengine.reset_integration(s.acc[nk][0])
+
+    def flush(self, stream_id: int) -> None:
+        """End the stream's open integration now (e.g. the last, partial
+        window of an aligned stream); its result arrives as usual."""
+        s = self.streams[stream_id]
+        self.sync()
+        if s.frames_in:
+            self._finish(s)
+            self.sync()
 
     def _complete(self) -> int:
         n = 0
@@ -303,10 +349,11 @@ class StreamServer:
                 fr.dev_packed = fr.dev_mask = None
             n += 1
         while self.outgoing and self.outgoing[0][0].query():
-            ev, s, k, index, frames = self.outgoing.popleft()
+            ev, s, k, index, frames, (q0, q1, win) = self.outgoing.popleft()
             hv, hc, ho = s.host[k]
             res = IntegrationResult(s.cfg.stream_id, index, frames, hv.numpy().copy(),
-                                    hc.numpy().copy(), ho.numpy().copy(), self._gpu_time(ev))
+                                    hc.numpy().copy(), ho.numpy().copy(), self._gpu_time(ev),
+                                    q0, q1, win)
             s.host_busy[k] = False
             self.results[s.cfg.stream_id].append(res)
             if self.on_result is not None:
@@ -354,6 +401,91 @@ class StreamServer:
             "hbm_peak_used": self.max_used,
             "admission_waits": self.admission_waits,
         }
+
+
+# ---------------------------------------------------------------------------
+# combining streams
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class CombinedIntegration:
+    """The integrations of several streams of one correlator over the same
+    sequence-number window, joined channel-wise in stream-id order."""
+    window: int
+    stream_ids: List[int]        # in channel order
+    channel_offsets: List[int]   # first channel of each stream
+    frames: List[int]            # frames each stream integrated
+    seq_first: int               # first and last frame sequence number seen
+    seq_last: int
+    vis: np.ndarray              # int32 [sum F][P][2]
+    count: np.ndarray            # int64 [sum F]
+    out: np.ndarray              # float32 [sum F][P][2]
+
+    def save(self, path: str) -> None:
+        """Dump to a .npz file: the three arrays plus the window, the stream
+        ids with their channel offsets and frame counts, and the sequence
+        range."""
+        np.savez(path, vis=self.vis, count=self.count, out=self.out,
+                 window=np.int64(self.window), stream_ids=np.asarray(self.stream_ids),
+                 channel_offsets=np.asarray(self.channel_offsets),
+                 frames=np.asarray(self.frames),
+                 seq=np.asarray([self.seq_first, self.seq_last], dtype=np.int64))
+
+
+class Combiner:
+    """Joins the aligned integrations of the streams of one correlator (the
+    same N, each stream its own channels), as the post-processing stage
+    combines the streams of a host: results are held per sequence-number
+    window until every stream has delivered that window, then concatenated
+    along the channel axis in increasing stream id.  Use ``add`` as the
+    server's ``on_result`` callback."""
+
+    def __init__(self, stream_ids, on_combined: Optional[Callable] = None):
+        self.ids = sorted(int(x) for x in stream_ids)
+        if len(set(self.ids)) != len(self.ids) or not self.ids:
+            raise ValueError("stream ids must be distinct and not empty")
+        self.on_combined = on_combined
+        self.held: Dict[int, Dict[int, IntegrationResult]] = {}
+        self.combined: List[CombinedIntegration] = []
+
+    def add(self, res: IntegrationResult) -> Optional[CombinedIntegration]:
+        if res.stream_id not in self.ids:
+            raise KeyError(f"stream {res.stream_id} is not combined here")
+        if res.window < 0:
+            raise ValueError("combining needs sequence-aligned streams (StreamConfig.aligned)")
+        parts = self.held.setdefault(res.window, {})
+        if res.stream_id in parts:
+            raise ValueError(f"stream {res.stream_id} delivered window {res.window} twice")
+        parts[res.stream_id] = res
+        if len(parts) < len(self.ids):
+            return None
+        del self.held[res.window]
+        c = self._join(res.window, [parts[i] for i in self.ids])
+        self.combined.append(c)
+        if self.on_combined is not None:
+            self.on_combined(c)
+        return c
+
+    def incomplete(self) -> Dict[int, List[int]]:
+        """Windows still waiting, with the streams that have not delivered."""
+        return {w: [i for i in self.ids if i not in parts] for w, parts in self.held.items()}
+
+    @staticmethod
+    def _join(window: int, parts: List[IntegrationResult]) -> CombinedIntegration:
+        P = parts[0].vis.shape[1]
+        if any(r.vis.shape[1] != P for r in parts):
+            raise ValueError("combined streams must have the same number of inputs")
+        offsets, off = [], 0
+        for r in parts:
+            offsets.append(off)
+            off += r.vis.shape[0]
+        return CombinedIntegration(
+            window=window, stream_ids=[r.stream_id for r in parts], channel_offsets=offsets,
+            frames=[r.frames for r in parts],
+            seq_first=min(r.seq_first for r in parts), seq_last=max(r.seq_last for r in parts),
+            vis=np.concatenate([r.vis for r in parts]),
+            count=np.concatenate([r.count for r in parts]),
+            out=np.concatenate([r.out for r in parts]))
 
 
 # ---------------------------------------------------------------------------
@@ -423,14 +555,20 @@ def run_load(specs, frames_per_stream: Optional[int] = None, integrations: int =
         server.open(StreamConfig(s.stream_id, s.N, s.F, s.T, B, s.frames_per_integration))
     stop = threading.Event()
 
+    late = []
+
     def produce():
+        # a frame's arrival is its scheduled Poisson time, so that time the
+        # producer spends behind schedule counts as queueing delay
         t0 = time.perf_counter()
         for t_off, sid, k in arrivals:
-            delay = t0 + t_off - time.perf_counter()
+            due = t0 + t_off
+            delay = due - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
             p, m = tens[sid][sequence[sid][k]]
-            server.submit(Frame(sid, k, p, m, time.perf_counter()))
+            late.append(max(0.0, time.perf_counter() - due))
+            server.submit(Frame(sid, k, p, m, due))
         stop.set()
 
     prod = threading.Thread(target=produce, daemon=True)
@@ -451,6 +589,10 @@ def run_load(specs, frames_per_stream: Optional[int] = None, integrations: int =
     st["offered_realized_gbps"] = bits / span / 1e9 if span > 0 else None
     st["arrival_span_s"] = span
     st["device_resident"] = device_resident
+    if late:
+        lt = np.array(late) * 1e3
+        st["submit_late_p50_ms"] = float(np.percentile(lt, 50))
+        st["submit_late_p99_ms"] = float(np.percentile(lt, 99))
     return LoadResult(server, st, pool, sequence)
 
 

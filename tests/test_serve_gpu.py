@@ -151,3 +151,70 @@ def test_device_resident_beats_plain_launches(srv, specs, pool):
     _say(f"served {res.stats['gbps']:.1f} Gb/s vs plain {plain['gbps']:.1f} Gb/s")
     assert res.stats["frames"] == n * len(specs)
     assert res.stats["p50_ms"] is not None and res.stats["p50_ms"] <= res.stats["p99_ms"]
+
+
+def test_aligned_streams_combined_by_stream_id(srv, orc):
+    """Streams of one correlator (same N, their own channels) integrate over
+    sequence-number windows of 2 frames; the combiner joins each window's
+    results in stream-id order.  One stream misses its first frame (its
+    window 0 holds one frame), frames are submitted with the streams
+    interleaved in a scrambled order, and every combined window equals the
+    oracle's sums of exactly the frames of that window, channel by channel;
+    the .npz dump reads back the same."""
+    import os
+    import tempfile
+    from paper_1503_06189_amd.serve import Combiner, Frame, StreamConfig, StreamServer
+    from paper_1503_06189_amd.synth import StreamSpec, stream_frame
+    N, T, B, L = 64, 512, 64, 2
+    specs = [StreamSpec(7, N, 3, T, L, 0.05, 1e9, 9001),
+             StreamSpec(2, N, 2, T, L, 0.05, 1e9, 9002),
+             StreamSpec(5, N, 4, T, L, 0.05, 1e9, 9003)]
+    seqs = {7: [0, 1, 2, 3, 4, 5], 2: [0, 1, 2, 3, 4, 5], 5: [1, 2, 3, 4, 5]}
+    frames = {s.stream_id: {q: stream_frame(s, q, B) for q in seqs[s.stream_id]} for s in specs}
+    comb = Combiner([s.stream_id for s in specs])
+    server = StreamServer(hbm_budget=1 << 30, on_result=comb.add)
+    for s in specs:
+        server.open(StreamConfig(s.stream_id, N, s.F, T, B, L, aligned=True))
+    order = [(q, s.stream_id) for q in range(6) for s in specs if q in seqs[s.stream_id]]
+    rng = np.random.default_rng(4)
+    # scramble across streams, keeping each stream's own frames in order
+    keys = {k: rng.random() for k in order}
+    order.sort(key=lambda k: (k[0] + keys[k] * 1.5))
+    for q, sid in order:
+        fr = frames[sid][q]
+        server.submit(Frame(sid, q, torch.from_numpy(fr.packed).cuda(),
+                            torch.from_numpy(fr.mask).cuda(), 0.0))
+        server.step()
+    server.sync()
+    for s in specs:
+        server.flush(s.stream_id)
+    torch.cuda.synchronize()
+    assert not comb.incomplete()
+    assert [c.window for c in comb.combined] == [0, 1, 2]
+    ids = sorted(s.stream_id for s in specs)
+    for c in comb.combined:
+        assert c.stream_ids == ids
+        want_v, want_n, frames_per = [], [], []
+        for sid in ids:
+            qs = [q for q in seqs[sid] if q // L == c.window]
+            frames_per.append(len(qs))
+            ev = en = None
+            for q in qs:
+                v, n = orc.correlate(frames[sid][q].packed, frames[sid][q].mask, B)
+                ev = v if ev is None else ev + v
+                en = n if en is None else en + n
+            want_v.append(ev)
+            want_n.append(en)
+        assert c.frames == frames_per
+        ev, en = np.concatenate(want_v), np.concatenate(want_n)
+        assert np.array_equal(c.count, en), f"window {c.window} counts"
+        assert np.array_equal(c.vis.astype(np.int64), ev), f"window {c.window} vis"
+        assert np.array_equal(c.out.view(np.uint32), orc.normalize(ev, en).view(np.uint32))
+        with tempfile.TemporaryDirectory() as d:
+            path = os.path.join(d, f"w{c.window}.npz")
+            c.save(path)
+            back = np.load(path)
+            assert np.array_equal(back["vis"], c.vis) and np.array_equal(back["out"], c.out)
+            assert list(back["stream_ids"]) == ids and int(back["window"]) == c.window
+    # stream 5 lacked frame 0: its window-0 integration holds one frame
+    assert comb.combined[0].frames == [2, 1, 2]
