@@ -435,10 +435,10 @@ xe_status launch_batch(xe_handle h, int slot, const SlotShape &sh, hipStream_t s
 namespace {
 
 // Work split of the flag Gram kernel: (channel, super-block pair, time
-// chunk); chunks of at least 4 stages, about two workgroups per compute
-// unit (two diagonal-pair workgroups share a CU; each chunk adds its counts
-// with atomics and reloads its pipeline, so chunks stay as long as that
-// allows).
+// chunk), about one workgroup per compute unit (a diagonal pair's
+// workgroup holds 96 KB of LDS counts, an off-diagonal one 156 KB), chunks
+// of at least 64 steps (four per wave), and at most the kernel's
+// validity window of 32768 samples, whose counts also fit 16 bits.
 xe::flag::Args flag_args(const uint32_t *flags, const uint8_t *mask, int32_t N, int32_t F,
                          int32_t T, int32_t B, int32_t *d, int n_cu) {
     using namespace xe::flag;
@@ -454,16 +454,14 @@ xe::flag::Args flag_args(const uint32_t *flags, const uint8_t *mask, int32_t N, 
     a.nblk = (T + B - 1) / B;
     a.ns = (N + 255) / 256;
     const int64_t units = (int64_t)F * (a.ns * (a.ns + 1) / 2);
-    const int64_t stages = (T + kStage - 1) / kStage;
-    int64_t want = (2 * (int64_t)std::max(n_cu, 1) + units - 1) / units;
-    const int64_t most = std::max<int64_t>(1, stages / 4);
+    const int64_t steps = (T + 31) / 32;
+    int64_t want = ((int64_t)std::max(n_cu, 1) + units - 1) / units;
+    const int64_t most = std::max<int64_t>(1, steps / 64);
     want = std::min(std::max<int64_t>(want, 1), most);
-    // a chunk's validity bits fit the kernel's LDS window
-    const int64_t max_stages = (int64_t)kWindow * 32 / kStage;
-    want = std::max(want, (stages + max_stages - 1) / max_stages);
-    const int64_t per = (stages + want - 1) / want;
-    a.chunks = (int)((stages + per - 1) / per);
-    a.chunk_samples = (int)(per * kStage);
+    want = std::max(want, (steps + kWindow - 1) / kWindow);
+    const int64_t per = (steps + want - 1) / want;
+    a.chunks = (int)((steps + per - 1) / per);
+    a.chunk_samples = (int)(per * 32);
     a.b_magic = B <= 65536 ? (((uint64_t)1 << 40) + (uint64_t)B - 1) / (uint64_t)B : 0;
     return a;
 }
@@ -650,10 +648,10 @@ xe_status xe_flag_accumulate(xe_handle h, const uint32_t *flags, const uint8_t *
     const int64_t diag_blocks = (int64_t)F * a.ns * a.chunks;
     const int64_t off_blocks = (int64_t)F * (a.ns * (a.ns - 1) / 2) * a.chunks;
     hipLaunchKernelGGL(xe::flag::gram_kernel<false>, dim3((unsigned)diag_blocks),
-                       dim3(xe::flag::kThreads), 0, (hipStream_t)stream, a);
+                       dim3(xe::flag::Shape<false>::kThreads), 0, (hipStream_t)stream, a);
     if (off_blocks > 0)
         hipLaunchKernelGGL(xe::flag::gram_kernel<true>, dim3((unsigned)off_blocks),
-                           dim3(xe::flag::kThreads), 0, (hipStream_t)stream, a);
+                           dim3(xe::flag::Shape<true>::kThreads), 0, (hipStream_t)stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "flag gram launch");
     return XE_OK;
