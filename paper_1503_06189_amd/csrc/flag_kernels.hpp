@@ -44,8 +44,6 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kSuper = 8;           // 32-input blocks per super block
 constexpr int kWindow = 1024;       // validity words per chunk: chunks <= 32768 samples
-constexpr int kColPitch = 17;       // words per tile column in LDS: 16 row pairs + 1
-constexpr int kTileWords = 32 * kColPitch;
 
 struct Args {
     const uint32_t *flags;   // [F][T][W]
@@ -67,7 +65,7 @@ __device__ __forceinline__ int block_of(const Args &a, int t) {
 
 // A diagonal pair (R == C) has 36 tiles of 32 x 32 counts (blocks bi <= bj)
 // and runs 16 waves; an off-diagonal pair (R < C) has 64 and runs 8 waves,
-// each side's words loaded by every wave.
+// and every wave loads the words of both super blocks.
 template <bool kOff>
 struct Shape {
     static constexpr int kSides = kOff ? 2 : 1;
@@ -75,16 +73,20 @@ struct Shape {
     static constexpr int kThreads = 64 * kWaves;
     static constexpr int kTiles = kOff ? 64 : 36;
     static constexpr int kBatch = kOff ? 4 : 8;   // steps a wave loads before it uses the first
+    static constexpr int kPitch = kOff ? 8 : 9;   // 64-bit words per tile column in LDS
+    static constexpr int kTileQuads = 32 * kPitch;
 };
 
-// Counts of the chunk in LDS as two 16-bit halves per word (a chunk holds at
-// most 32768 samples, so no half carries into the other): tile k, column j,
-// row pair p at acc[k][j * kColPitch + p], low half row 2p.  The odd pitch
-// spreads the two half-waves of an MFMA result over different banks.
+// Counts of the chunk in LDS as four 16-bit fields per 64-bit word (a chunk
+// holds at most 32768 samples, so no field carries into the next): tile k,
+// column j, rows 4 Q .. 4 Q + 3 at acc[k][j * kPitch + Q], row 4 Q in the
+// low field.  The diagonal pair's odd pitch spreads the two half-waves of
+// an MFMA result over different banks.
 template <bool kOff>
 struct Lds {
-    uint32_t acc[Shape<kOff>::kTiles * kTileWords];
-    uint32_t words[Shape<kOff>::kWaves][Shape<kOff>::kSides][kSuper][32];  // one step, per wave
+    using S = Shape<kOff>;
+    uint64_t acc[S::kTiles * S::kTileQuads];
+    uint32_t words[S::kWaves][S::kSides][kSuper][32];  // per wave: its current step
     uint32_t valid[kWindow];   // bit k of word s: sample 32 s + k of the chunk
 };
 
@@ -122,15 +124,17 @@ __device__ __forceinline__ v4i build_op(const uint32_t *src, int lane) {
     return out;
 }
 
-// Add one step's 32 x 32 counts (an MFMA result: element v at row
-// 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32) into LDS tile `t`, two
-// rows per word.
-__device__ __forceinline__ void add_tile(uint32_t *t, const v16i &c, int lane) {
-    uint32_t *col = t + (lane & 31) * kColPitch + 2 * (lane >> 5);
+// Add a 32 x 32 block of counts (an MFMA result: element v at row
+// 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32) into LDS tile `t`, four rows
+// per 64-bit word.
+template <int PITCH>
+__device__ __forceinline__ void add_tile(uint64_t *t, const v16i &c, int lane) {
+    uint64_t *col = t + (lane & 31) * PITCH + (lane >> 5);
 #pragma unroll
-    for (int v = 0; v < 16; v += 2) {
-        const int p = 4 * (v >> 2) + ((v & 3) >> 1);   // row pair without the half-wave's 2
-        atomicAdd(col + p, (uint32_t)c[v] | ((uint32_t)c[v + 1] << 16));
+    for (int q = 0; q < 4; ++q) {
+        const uint64_t lo = (uint32_t)c[4 * q] | ((uint32_t)c[4 * q + 1] << 16);
+        const uint64_t hi = (uint32_t)c[4 * q + 2] | ((uint32_t)c[4 * q + 3] << 16);
+        atomicAdd((unsigned long long *)(col + 2 * q), (unsigned long long)(lo | (hi << 32)));
     }
 }
 
@@ -168,6 +172,34 @@ __device__ __forceinline__ void fill_window(const Args &a, Lds<kOff> &L, int f, 
     }
 }
 
+// The words of kBatch steps, step q at byte row0 + q * step_bytes of the
+// buffer (steps past its range read 0), all loads issued before any is
+// used: four dwords per side, or one 16-byte load when kVec (the four words
+// of a side are contiguous and 16-byte aligned).
+template <bool kVec, int kBatch, int SIDES>
+__device__ __forceinline__ void load_batch(uint32_t (&raw)[kBatch][SIDES][4],
+                                           __amdgpu_buffer_rsrc_t rsrc,
+                                           const uint32_t (&off)[SIDES][4], uint32_t row0,
+                                           uint32_t step_bytes) {
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q)
+#pragma unroll
+        for (int side = 0; side < SIDES; ++side) {
+            const uint32_t o = row0 + q * step_bytes;
+            if (kVec) {
+                const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(o + off[side][0]),
+                                                                    0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) raw[q][side][r] = (uint32_t)v[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    raw[q][side][r] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
+                        rsrc, (int)(o + off[side][r]), 0, 0);
+            }
+        }
+}
+
 // Workgroup b runs on XCD b % 8; consecutive work items (the chunks of one
 // channel and pair) are numbered onto one XCD so they share its L2.
 __device__ __forceinline__ int64_t xcd_local(int64_t b, int64_t total) {
@@ -178,20 +210,22 @@ __device__ __forceinline__ int64_t xcd_local(int64_t b, int64_t total) {
 
 // One workgroup: channel f, super-block pair (R, C), one time chunk.  Every
 // wave takes its own 32-sample steps of the chunk (wave, wave + waves, ...),
-// kBatch steps' loads in flight at once, and never waits for another wave:
+// kBatch steps' loads in flight at once (the first batch issued before the
+// workgroup's set-up), and never waits for another wave:
 //   * lane l holds sample l / 2 of the step and words 4 (l % 2) .. +3 of
 //     each super block, masked by the sample's validity and the inputs < N;
-//   * one ballot per word tells which 32-input blocks hold a flag; a step
-//     without any (the common case for the sparse flags of the method) ends
-//     there, the counterpart of the method's test of whole 32-bit words;
-//   * otherwise the wave stores the step's words in its own LDS slot, builds
-//     the MFMA operand of every flagged block, and runs one
-//     v_mfma_i32_32x32x32_i8 per tile whose two blocks are both flagged,
-//     adding the 32 x 32 counts into the workgroup's LDS tiles.
+//   * one ballot tells whether the step holds any flag; a step without any
+//     (the common case for the sparse flags of the method) ends there, the
+//     counterpart of the method's test of whole 32-bit words;
+//   * otherwise one ballot per word tells which 32-input blocks hold a flag,
+//     the wave stores the step's words in its own LDS slot, builds the MFMA
+//     operand of every flagged block, and runs one v_mfma_i32_32x32x32_i8 per
+//     tile whose two blocks both hold a flag, adding the 32 x 32 counts into
+//     the workgroup's LDS counts.
 // After a barrier, the nonzero counts are added into d with integer atomics
 // (time chunks of one pair add into the same counts; the order does not
 // matter).
-template <bool kOff>
+template <bool kOff, bool kVec>
 __global__ __launch_bounds__(Shape<kOff>::kThreads) void gram_kernel(Args a) {
     using S = Shape<kOff>;
     constexpr int SIDES = S::kSides;
@@ -223,14 +257,6 @@ __global__ __launch_bounds__(Shape<kOff>::kThreads) void gram_kernel(Args a) {
     const int t_end = __builtin_amdgcn_readfirstlane(min(a.T, t_begin + a.chunk_samples));
     const int nsteps = (t_end - t_begin + 31) >> 5;
 
-    // clear the counts, build the validity window
-    {
-        uint4 *z = (uint4 *)L.acc;
-        for (int e = tid; e < S::kTiles * kTileWords / 4; e += S::kThreads)
-            z[e] = (uint4){0u, 0u, 0u, 0u};
-    }
-    fill_window(a, L, f, t_begin, t_end, tid);
-
     // the chunk's rows of this channel's flags through a buffer resource
     // whose range ends at the chunk's last sample: loads past it return 0
     // without a memory access
@@ -245,8 +271,9 @@ __global__ __launch_bounds__(Shape<kOff>::kThreads) void gram_kernel(Args a) {
     void *bp = (void *)(uintptr_t)(((uint64_t)base_hi << 32) | base_lo);
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc(bp, (short)0, (int)extent, 0x00020000);
-    // per lane: byte offset of each word within a row (word clamped to
-    // W - 1) and the bits of inputs < N
+    // per lane: byte offset of each word within a row and the bits of
+    // inputs < N; a word past the row reads the last word (kVec: the last
+    // four), masked to 0
     uint32_t off[SIDES][4], pad[SIDES][4];
 #pragma unroll
     for (int side = 0; side < SIDES; ++side)
@@ -254,56 +281,72 @@ __global__ __launch_bounds__(Shape<kOff>::kThreads) void gram_kernel(Args a) {
         for (int r = 0; r < 4; ++r) {
             const int gw = (side == 0 ? R : C) * kSuper + 4 * (lane & 1) + r;
             const int left = a.N - gw * 32;
-            off[side][r] = 4u * (uint32_t)min(gw, a.W - 1);
+            off[side][r] = kVec ? 4u * (uint32_t)min(gw - r, a.W - 4) + 4u * r
+                                : 4u * (uint32_t)min(gw, a.W - 1);
             pad[side][r] = left >= 32 ? 0xffffffffu : left > 0 ? (1u << left) - 1u : 0u;
         }
     const uint32_t smp = (uint32_t)(lane >> 1);
-    uint32_t(*slot)[kSuper][32] = L.words[wave];
+    const uint32_t step_bytes = 32u * S::kWaves * row_bytes;
+    auto batch_row = [&](int j0) {
+        return (32u * (uint32_t)(wave + S::kWaves * j0) + smp) * row_bytes;
+    };
+    uint32_t raw[S::kBatch][SIDES][4];
+    load_batch<kVec, S::kBatch, SIDES>(raw, rsrc, off, batch_row(0), step_bytes);
+
+    // clear the counts, build the validity window
+    {
+        uint4 *z = (uint4 *)L.acc;
+        for (int e = tid; e < S::kTiles * S::kTileQuads / 2; e += S::kThreads)
+            z[e] = (uint4){0u, 0u, 0u, 0u};
+    }
+    fill_window(a, L, f, t_begin, t_end, tid);
     __syncthreads();   // counts cleared, validity window visible
 
     constexpr uint64_t kEven = 0x5555555555555555ull;
+    constexpr int cs = SIDES - 1;   // side of the column blocks
+    uint32_t(*slot)[kSuper][32] = L.words[wave];
     for (int j0 = 0; wave + S::kWaves * j0 < nsteps; j0 += S::kBatch) {
-        uint32_t raw[S::kBatch][SIDES][4];
-#pragma unroll
-        for (int q = 0; q < S::kBatch; ++q) {
-            // steps past the chunk read past the buffer's range: 0
-            const uint32_t row = (32u * (uint32_t)(wave + S::kWaves * (j0 + q)) + smp) * row_bytes;
-#pragma unroll
-            for (int side = 0; side < SIDES; ++side)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    raw[q][side][r] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
-                        rsrc, (int)(row + off[side][r]), 0, 0);
-        }
+        if (j0 > 0) load_batch<kVec, S::kBatch, SIDES>(raw, rsrc, off, batch_row(j0), step_bytes);
 #pragma unroll
         for (int q = 0; q < S::kBatch; ++q) {
             const int s = wave + S::kWaves * (j0 + q);
-            if (s >= nsteps) break;
+            if (s >= nsteps) continue;
             const uint32_t keep = 0u - ((L.valid[s] >> smp) & 1u);
-            uint32_t v[SIDES][4];
-            uint32_t blk[SIDES];   // bit b: block b of the side holds a flag in this step
+            uint32_t seen[SIDES];
 #pragma unroll
             for (int side = 0; side < SIDES; ++side) {
-                blk[side] = 0;
+                seen[side] = 0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    v[side][r] = raw[q][side][r] & pad[side][r] & keep;
-                    const uint64_t m = __ballot(v[side][r] != 0u);
-                    blk[side] |= ((m & kEven) != 0 ? 1u : 0u) << r;
-                    blk[side] |= ((m & ~kEven) != 0 ? 1u : 0u) << (4 + r);
+                    raw[q][side][r] &= pad[side][r] & keep;
+                    seen[side] |= raw[q][side][r];
                 }
-                blk[side] = __builtin_amdgcn_readfirstlane(blk[side]);
             }
-            if (blk[0] == 0u || blk[SIDES - 1] == 0u) continue;
+            bool flagged = true;
+#pragma unroll
+            for (int side = 0; side < SIDES; ++side) flagged = flagged && __ballot(seen[side] != 0u) != 0;
+            if (!flagged) continue;
+            // bit b of blk[side]: block b of the side holds a flag
+            uint32_t blk[SIDES];
+#pragma unroll
+            for (int side = 0; side < SIDES; ++side) {
+                uint32_t bits = 0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint64_t m = __ballot(raw[q][side][r] != 0u);
+                    bits |= ((m & kEven) != 0 ? 1u : 0u) << r;
+                    bits |= ((m & ~kEven) != 0 ? 1u : 0u) << (4 + r);
+                }
+                blk[side] = __builtin_amdgcn_readfirstlane(bits);
+            }
             // the step's words in this wave's slot, [side][block][sample]
 #pragma unroll
             for (int side = 0; side < SIDES; ++side)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) slot[side][4 * (lane & 1) + r][smp] = v[side][r];
+                for (int r = 0; r < 4; ++r) slot[side][4 * (lane & 1) + r][smp] = raw[q][side][r];
             // operands of the column side's flagged blocks; a row block's
             // operand is the same (diagonal pair) or built when its row of
             // tiles comes
-            const int cs = SIDES - 1;
             v4i op[kSuper];
 #pragma unroll
             for (int b = 0; b < kSuper; ++b)
@@ -318,7 +361,8 @@ __global__ __launch_bounds__(Shape<kOff>::kThreads) void gram_kernel(Args a) {
                     if (((blk[cs] >> bj) & 1u) == 0u) continue;
                     const int k = kOff ? bi * kSuper + bj
                                        : bi * kSuper - bi * (bi - 1) / 2 + (bj - bi);
-                    add_tile(L.acc + k * kTileWords, mfma(row_op, op[bj], zero), lane);
+                    add_tile<S::kPitch>(L.acc + k * S::kTileQuads, mfma(row_op, op[bj], zero),
+                                        lane);
                 }
             }
         }
@@ -328,9 +372,9 @@ __global__ __launch_bounds__(Shape<kOff>::kThreads) void gram_kernel(Args a) {
     // the nonzero counts into d
     const int64_t P = (int64_t)a.N * (a.N + 1) / 2;
     int32_t *dst = a.d + (int64_t)f * P;
-    for (int e = tid; e < S::kTiles * 512; e += S::kThreads) {
-        const int k = e >> 9, j = (e >> 4) & 31, p = e & 15;
-        const uint32_t word = L.acc[k * kTileWords + j * kColPitch + p];
+    for (int e = tid; e < S::kTiles * 256; e += S::kThreads) {
+        const int k = e >> 8, j = (e >> 3) & 31, Q = e & 7;
+        const uint64_t word = L.acc[k * S::kTileQuads + j * S::kPitch + Q];
         if (word == 0u) continue;
         int bi, bj;
         if (kOff) {
@@ -345,10 +389,13 @@ __global__ __launch_bounds__(Shape<kOff>::kThreads) void gram_kernel(Args a) {
             }
             bj = bi + kk;
         }
-        const int gi = R * 256 + bi * 32 + 2 * p, gj = C * 256 + bj * 32 + j;
-        const int lo = (int)(word & 0xffffu), hi = (int)(word >> 16);
-        if (lo != 0 && gi <= gj && gj < a.N) atomicAdd(dst + tri(a.N, gi, gj), lo);
-        if (hi != 0 && gi + 1 <= gj && gj < a.N) atomicAdd(dst + tri(a.N, gi + 1, gj), hi);
+        const int gi = R * 256 + bi * 32 + 4 * Q, gj = C * 256 + bj * 32 + j;
+        if (gj >= a.N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int cnt = (int)((word >> (16 * r)) & 0xffffu);
+            if (cnt != 0 && gi + r <= gj) atomicAdd(dst + tri(a.N, gi + r, gj), cnt);
+        }
     }
 }
 
