@@ -256,8 +256,9 @@ def batched_leg(torch, reps: int):
         for it in items:
             xengine.accumulate(*it, handle=h, stream=stream)
 
-    chunk = tune.tune(items, handle=h)
-    plan = xengine.BatchPlan(items, chunk_steps=chunk, handle=h)
+    choice = tune.tune(items, handle=h)
+    plan = xengine.BatchPlan(items, chunk_steps=choice.chunk_steps, handle=h,
+                             geometry=choice.geometry)
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
     side.wait_stream(stream)
@@ -295,7 +296,8 @@ def batched_leg(torch, reps: int):
         "plain_gbps": round(bits / (ms_plain / 1e3) / 1e9, 1),
         "tops": round(ops / (ms_graph / 1e3) / 1e12, 1),
         "mfma_frac": round(ops / (ms_graph / 1e3) / 1e12 / MFMA_INT8_PEAK_TOPS, 4),
-        "chunk_steps": chunk,
+        "chunk_steps": choice.chunk_steps,
+        "geometry": choice.geometry,
         "exact_vs_plain": bool(exact),
     }
 

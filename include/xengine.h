@@ -91,6 +91,22 @@ const char *xe_status_string(xe_status s);
  * next call on the handle. */
 const char *xe_last_error(xe_handle h);
 
+/* Tile geometry of frames with N <= 128 (at most four 32-input blocks).
+ * The correlation of Sec. II-B runs 32 x 32 tile MFMAs in groups of eight
+ * waves; a frame of at most four blocks has only the 10 tiles of a 4-block
+ * triangle.  XE_GEOM_SUPER pads it to a 256-input super-block (36 tiles,
+ * one 32-sample step per loop step); XE_GEOM_HALVES computes the 10 tiles
+ * twice per loop step, over two consecutive 32-sample steps, and adds the
+ * two halves; XE_GEOM_AUTO (the default) is XE_GEOM_HALVES.  Larger frames
+ * are not affected.  Set per handle; it applies to later correlation calls
+ * and to batch plans built afterwards (a plan keeps the geometry it was
+ * built with).  The results are identical.  Errors: XE_ERR_ARG (NULL
+ * handle, unknown value). */
+#define XE_GEOM_AUTO 0
+#define XE_GEOM_SUPER 1
+#define XE_GEOM_HALVES 2
+xe_status xe_set_geometry(xe_handle h, int32_t geometry);
+
 /* Correlate one frame and OVERWRITE vis and count with its sums
  * (Sec. II-B: correlation of a staged frame; Sec. II-C: the loss counter).
  * 1 <= N <= XE_MAX_N, F >= 1, F * N <= XE_MAX_FN, 1 <= T <= XE_MAX_SAMPLES,

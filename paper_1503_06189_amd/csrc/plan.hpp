@@ -19,6 +19,14 @@
 // halves each: ns^2 groups.  Each workgroup integrates its tiles over one
 // chunk of the frame's time samples; chunk 0 writes the output and a merge
 // kernel adds the other chunks.
+//
+// Second geometry ("halves", for N <= 128, at most 4 input blocks): the
+// padded super-block would compute 36 tiles for the 10 of the 4-block
+// triangle.  Instead the 8 staged slots hold blocks 0..3 at two consecutive
+// 32-sample steps (slots 4..7 one step later), so a loop step covers 64
+// samples: waves 4 and 5 integrate the triangle over the even steps, waves
+// 6 and 7 over the odd ones, and the rectangle waves only stage.  At the end
+// waves 6 and 7 hand their sums to 4 and 5 through LDS, which write them.
 #pragma once
 
 #include <stdint.h>
@@ -43,16 +51,18 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kMaxStepsPerChunk = 1 << 18;
 // Raw bytes are loaded this many steps ahead of their use; a chunk is run
 // in whole rings of kDepth steps (the last ring padded with zeros), so the
-// byte offsets of a chunk plus 2 * kDepth steps must stay below 2^31.
+// byte offsets of a chunk plus 4 * kDepth 32-sample steps must stay below
+// 2^31.
 #ifndef XE_DEPTH
 #define XE_DEPTH 4
 #endif
 constexpr int kDepth = XE_DEPTH;
 
-// longest chunk (in steps) whose byte offsets, lookahead included, stay
-// below 2^31 for F channels of N inputs
+// longest chunk (in steps) whose byte offsets, lookahead included (twice the
+// ring in 32-sample steps: a halves loop step covers two), stay below 2^31
+// for F channels of N inputs
 inline int64_t max_steps_per_chunk(int64_t F, int64_t N) {
-    int64_t m = (((int64_t)1 << 31) - 1) / (F * N * kStep) - 2 * kDepth;
+    int64_t m = (((int64_t)1 << 31) - 1) / (F * N * kStep) - 4 * kDepth;
     if (m > kMaxStepsPerChunk) m = kMaxStepsPerChunk;
     return m - m % kDepth;
 }
@@ -64,11 +74,16 @@ inline int round_steps(int sps) { return (sps + kDepth - 1) / kDepth * kDepth; }
 // device).  Slot s of the staged blocks holds input block
 //   diagonal:      rbase + s                       (s < nslots)
 //   off-diagonal:  rbase + s for s < 4, cbase + s - 4 otherwise
+//   halves:        s % 4 (slots 4..7 one step later)
 struct Group {
     int diag;
+    int small;   // the halves geometry
     int rbase, cbase;
     int nslots;
 };
+
+// the halves geometry applies to frames of at most 4 input blocks
+XE_HD inline int use_halves(int halves, int nb) { return halves && nb <= 4 ? 1 : 0; }
 
 XE_HD inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
@@ -90,11 +105,13 @@ XE_HD inline void offdiag_pair(int ns, int p, int *R, int *C) {
     *C = r + 1 + p;
 }
 
-XE_HD inline Group make_group(int nb, int gid) {
+XE_HD inline Group make_group(int nb, int gid, int halves) {
     Group g;
     int ns = super_rows(nb);
+    g.small = 0;
     if (gid < ns) {
         g.diag = 1;
+        g.small = use_halves(halves, nb);
         g.rbase = g.cbase = gid * kSuper;
         g.nslots = kSuper;  // blocks past the last one are staged as zeros
     } else {
@@ -110,12 +127,15 @@ XE_HD inline Group make_group(int nb, int gid) {
 }
 
 XE_HD inline int slot_block(const Group &g, int s) {
+    if (g.small) return s & 3;
     return (g.diag || s < 4) ? g.rbase + s : g.cbase + (s - 4);
 }
 
 // 32x32 tiles computed per channel: 36 per diagonal group (8 x 9), 32 per
-// off-diagonal half (4 x 8); padded tiles past N included.
-inline int64_t tiles_per_channel(int nb) {
+// off-diagonal half (4 x 8); padded tiles past N included.  The halves
+// geometry computes the 10 tiles of the 4-block triangle.
+inline int64_t tiles_per_channel(int nb, int halves) {
+    if (use_halves(halves, nb)) return 10;
     int64_t ns = super_rows(nb);
     return ns * 36 + ns * (ns - 1) * 32;
 }

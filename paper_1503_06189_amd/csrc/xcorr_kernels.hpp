@@ -71,6 +71,7 @@ struct CorrArgs {
     int groups;           // groups per channel
     int splits;
     int steps_per_split;
+    int halves;           // the halves geometry when N <= 128
 };
 
 // ---------------------------------------------------------------------------
@@ -154,6 +155,7 @@ struct Unit {
     uint32_t voff;  // byte offset of (sample 4 sq, input n0) within the chunk;
                     // out of range (reads 0) when the inputs lie past N
     bool act;       // inputs lie below N (else staged as 0)
+    bool hi;        // halves geometry, slots 4..7: the odd step of the pair
     uint32_t inb;   // unaligned path: byte c of the dword lies below N
 };
 
@@ -247,20 +249,24 @@ __device__ inline void fill_mask_window(const CorrArgs &a, int f, const Chunk &c
     }
 }
 
-// Decode one prefetched step into LDS.  Per input, from the masked nibbles
+// Decode one prefetched step into LDS (validity words vb0 for its units, vb1
+// for the odd-step units of the halves geometry).  Per input, from the
+// masked nibbles
 // A' = a + 8 and B' = b + 8 (4 samples per dword):
 //   Xr = (a | b)             a = (A' + 0x78) ^ 0x80
 //   Xs = (a + b | b - a)     a + b = (A' + B' + 0x70) ^ 0x80,
 //                            b - a = ((B' | 0x80) - A') ^ 0x80
 // all per byte without carries or borrows; Xs only for diagonal groups.
 // A unit writes bytes 8h .. 8h+7 of its inputs' chunks (h = sq & 1).
-template <bool kXs, int UPT>
+template <bool kXs, bool kSmall, int UPT>
 __device__ __forceinline__ void commit(const Unit (&u)[UPT], const Prefetch<UPT> &p,
-                                       uint32_t vbits, uint8_t *buf, int slot_bytes) {
+                                       uint32_t vb0, uint32_t vb1, uint8_t *buf,
+                                       int slot_bytes) {
 #pragma unroll
     for (int r = 0; r < UPT; ++r) {
         uint32_t L[4];
         transpose4(p.d[r], L);
+        const uint32_t vbits = kSmall && u[r].hi ? vb1 : vb0;
         const uint32_t vq = u[r].act ? (vbits >> (4 * u[r].sq)) & 15u : 0u;
         const uint32_t m = bits_to_bytes(vq);
         const int o = u[r].sq >> 1, h = u[r].sq & 1;
@@ -361,7 +367,9 @@ __device__ __forceinline__ void read_ops(const uint8_t *buf, int slot_bytes, int
 }
 
 // One loop step: the 16 MFMAs of step s, with the decode of step s + 2
-// woven into them and the operands of the next sub-steps read ahead.
+// woven into them and the operands of the next sub-steps read ahead
+// (kMma = false: the decode only, for the rectangle waves of the halves
+// geometry, whose tiles would pair different time steps).
 //   * (s, sub 0) operands arrive in `o`, read during the previous step;
 //     (s, sub 1) operands are read at the start; (s + 1, sub 0) operands
 //     are read into `o` once the sub-0 MFMAs have taken theirs, so the next
@@ -371,19 +379,19 @@ __device__ __forceinline__ void read_ops(const uint8_t *buf, int slot_bytes, int
 //     first 14 of them so the last LDS write lands before the barrier.  A
 //     piece's VALU work issues while the MFMA before it occupies the matrix
 //     core; scheduling barriers keep the order.
-template <int SHAPE, bool kXs, int UPT>
+template <int SHAPE, bool kXs, int UPT, bool kMma, bool kSmall>
 __device__ __forceinline__ void pipelined_step(const uint8_t *cur, const uint8_t *next,
                                                uint8_t *dec, int slot_bytes, int s0, int c0,
                                                Acc<SHAPE> &acc, const Unit (&u)[UPT],
-                                               const Prefetch<UPT> &p, uint32_t vbits,
-                                               Ops<SHAPE> &o) {
+                                               const Prefetch<UPT> &p, uint32_t vb0,
+                                               uint32_t vb1, Ops<SHAPE> &o) {
     // 5 pieces: the transposes of all units, then input c of all units;
     // the units' chains are independent, so a piece has UPT-fold ILP
     constexpr int kPieces = 5;
     constexpr int kSpan = 14;
     using TL = Tiles<SHAPE>;
     Ops<SHAPE> o1;
-    read_ops(cur, slot_bytes, s0, c0, 1, o1);
+    if (kMma) read_ops(cur, slot_bytes, s0, c0, 1, o1);
     // decode state
     uint32_t L[UPT][4];
     uint32_t msk[UPT];
@@ -393,6 +401,7 @@ __device__ __forceinline__ void pipelined_step(const uint8_t *cur, const uint8_t
 #pragma unroll
             for (int r = 0; r < UPT; ++r) {
                 transpose4(p.d[r], L[r]);
+                const uint32_t vbits = kSmall && u[r].hi ? vb1 : vb0;
                 const uint32_t vq = u[r].act ? (vbits >> (4 * u[r].sq)) & 15u : 0u;
                 msk[r] = bits_to_bytes(vq);
             }
@@ -443,15 +452,17 @@ __device__ __forceinline__ void pipelined_step(const uint8_t *cur, const uint8_t
         }
     };
 
-    rows_xp(o);
+    if (kMma) rows_xp(o);
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-        if (m == 8) rows_xp(o1);
-        if (m == 9) read_ops(next, slot_bytes, s0, c0, 0, o);
-        if (m < 8)
-            mfma_op(o, m);
-        else
-            mfma_op(o1, m - 8);
+        if (kMma) {
+            if (m == 8) rows_xp(o1);
+            if (m == 9) read_ops(next, slot_bytes, s0, c0, 0, o);
+            if (m < 8)
+                mfma_op(o, m);
+            else
+                mfma_op(o1, m - 8);
+        }
 #pragma unroll
         for (int q = 0; q < kPieces; ++q)
             if (q * kSpan / kPieces == m) piece(q);
@@ -494,14 +505,30 @@ struct TileMap {
 // The role of wave `wave` in a tile group: its staging share, tile shape and
 // first row / column slot.  Waves w and w + 4 share a SIMD: each SIMD gets
 // one rectangle and (diagonal group) one half triangle.
-template <int NSLOT_, int SHAPE_, int UPT_>
+template <int NSLOT_, int SHAPE_, int UPT_, bool kMma_ = true, bool kSmall_ = false>
 struct Role {
     static constexpr int NSLOT = NSLOT_, SHAPE = SHAPE_, UPT = UPT_;
+    static constexpr bool kMma = kMma_;     // runs MFMAs (else stages only)
+    static constexpr bool kSmall = kSmall_;  // the halves geometry
 };
 
-template <class Fn>
+// Which role sets a caller instantiates: kAllKinds (decides per group), or
+// only the groups of one geometry (the two persistent batch kernels, so
+// that each is register-allocated for its own roles).
+enum Kinds { kAllKinds = 0, kSuperOnly = 1, kHalvesOnly = 2 };
+
+template <int KINDS = kAllKinds, class Fn>
 __device__ __forceinline__ void with_role(const Group &g, int wave, Fn &&fn) {
-    if (g.diag) {
+    if (KINDS == kHalvesOnly || (KINDS == kAllKinds && g.diag && g.small)) {
+        // halves geometry: the rectangle waves stage only; waves 4, 5 take
+        // the triangle of slots 0..3 (even steps), waves 6, 7 of 4..7 (odd)
+        if (wave < 4)
+            fn(Role<8, kRect, 1, false, true>{}, wave, 4);
+        else if ((wave & 1) == 0)
+            fn(Role<8, kTriA, 1, true, true>{}, 2 * (wave - 4), 0);
+        else
+            fn(Role<8, kTriB, 1, true, true>{}, 2 * (wave - 5), 0);
+    } else if (g.diag) {
         if (wave < 4)  // row block `wave` x columns 4..7
             fn(Role<8, kRect, 1>{}, wave, 4);
         else if ((wave & 1) == 0)  // triangle of blocks 0..3 (wave 4) or 4..7 (wave 6)
@@ -578,7 +605,7 @@ __device__ __forceinline__ void split_q(const v16i &q, int32_t *tbuf, v16i &re, 
 // UPT = staging units per lane and step (wave-rounds of 64 units): the
 // 16 (diagonal) or 24 (off-diagonal) wave-rounds of a step are dealt to the
 // 8 waves as x = r * 8 + wave.
-template <bool kAligned, bool kOverwrite, int NSLOT, int SHAPE, int UPT>
+template <bool kAligned, bool kOverwrite, int NSLOT, int SHAPE, int UPT, bool kMma, bool kSmall>
 __device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int f, int gid,
                                          int split, int s0, int c0, uint8_t *lds,
                                          uint32_t *mwords) {
@@ -591,7 +618,12 @@ __device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int 
     const int t_begin = split * a.steps_per_split * kStep;
     int t_end = t_begin + a.steps_per_split * kStep;
     if (t_end > a.T) t_end = a.T;
-    const int nsteps = (t_end - t_begin + kStep - 1) / kStep;
+    // 32-sample steps of the chunk, and loop steps: one 32-sample step, or
+    // a pair of them in the halves geometry
+    const int nsteps32 = (t_end - t_begin + kStep - 1) / kStep;
+    constexpr int pair = kSmall ? 2 : 1;
+    const int nsteps = (nsteps32 + pair - 1) / pair;
+    constexpr int step_samples = pair * kStep;
 
     const Chunk ch = make_chunk(a, f, t_begin, t_end);
     Unit u[UPT];
@@ -605,7 +637,9 @@ __device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int 
         u[r].sq = 2 * o + h;
         int n0 = slot_block(g, u[r].s) * kBlk + 4 * u[r].q;
         u[r].act = n0 < a.N;
-        u[r].voff = u[r].act ? (uint32_t)(4 * u[r].sq) * ch.row_bytes + (uint32_t)n0
+        u[r].hi = kSmall && u[r].s >= 4;
+        u[r].voff = u[r].act ? (uint32_t)(4 * u[r].sq + (u[r].hi ? kStep : 0)) * ch.row_bytes +
+                                   (uint32_t)n0
                              : 0x80000000u;
         u[r].inb = 0;
 #pragma unroll
@@ -632,39 +666,43 @@ __device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int 
     static_assert(D >= 3, "the ring must hold the step being decoded and two in flight");
     // validity words: a window of kMaskWindow steps in LDS; each lane caches
     // the word of one of the next 64 steps, read out with readlane
-    fill_mask_window(a, f, ch, 0, nsteps, mwords);
+    // (in 32-sample steps: loop step j uses word j, or words 2j and 2j + 1)
+    fill_mask_window(a, f, ch, 0, nsteps32, mwords);
     Prefetch<UPT> pf[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) issue_loads<kAligned>(ch, t_begin + k * kStep, u, pf[k]);
+    for (int k = 0; k < D; ++k) issue_loads<kAligned>(ch, t_begin + k * step_samples, u, pf[k]);
     __syncthreads();
     uint32_t mcache = mwords[lane];
-    auto vbits_of = [&](int j) -> uint32_t {
-        return j < nsteps ? (uint32_t)__builtin_amdgcn_readlane((int)mcache, j & 63) : 0u;
+    auto vbits_of = [&](int j32) -> uint32_t {
+        return j32 < nsteps32 ? (uint32_t)__builtin_amdgcn_readlane((int)mcache, j32 & 63) : 0u;
     };
-    commit<kDiagGroup>(u, pf[0], vbits_of(0), lds, SLOT);
-    commit<kDiagGroup>(u, pf[1], vbits_of(1), lds + kBufBytes, SLOT);
+    commit<kDiagGroup, kSmall>(u, pf[0], vbits_of(0), vbits_of(pair - 1), lds, SLOT);
+    commit<kDiagGroup, kSmall>(u, pf[1], vbits_of(pair), vbits_of(2 * pair - 1),
+                               lds + kBufBytes, SLOT);
     __syncthreads();
     Ops<SHAPE> ops;
-    read_ops(lds, SLOT, s0, c0, 0, ops);
+    if (kMma) read_ops(lds, SLOT, s0, c0, 0, ops);
     int b_cur = 0, b_next = kBufBytes, b_dec = 2 * kBufBytes;  // LDS byte offsets
     const int npad = (nsteps + D - 1) / D * D;
     for (int sb = 0; sb < npad; sb += D) {
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const int s = sb + k;
-            const int j = s + 2;  // step decoded now
-            if ((j & 63) == 0 && j < nsteps) {
-                if (j % kMaskWindow == 0) {
+            const int j = s + 2;   // step decoded now
+            const int j32 = pair * j;
+            if ((j32 & 63) == 0 && j32 < nsteps32) {
+                if (j32 % kMaskWindow == 0) {
                     // next window of validity words (uniform branch, rare)
-                    fill_mask_window(a, f, ch, j, nsteps, mwords);
+                    fill_mask_window(a, f, ch, j32, nsteps32, mwords);
                     __syncthreads();
                 }
-                mcache = mwords[(j % kMaskWindow) + lane];
+                mcache = mwords[(j32 % kMaskWindow) + lane];
             }
-            const uint32_t vbits = vbits_of(j);
-            issue_loads<kAligned>(ch, t_begin + (s + D) * kStep, u, pf[k]);
-            pipelined_step<SHAPE, kDiagGroup>(lds + b_cur, lds + b_next, lds + b_dec, SLOT, s0,
-                                              c0, acc, u, pf[(k + 2) % D], vbits, ops);
+            const uint32_t vb0 = vbits_of(j32), vb1 = kSmall ? vbits_of(j32 + 1) : vb0;
+            issue_loads<kAligned>(ch, t_begin + (s + D) * step_samples, u, pf[k]);
+            pipelined_step<SHAPE, kDiagGroup, UPT, kMma, kSmall>(
+                lds + b_cur, lds + b_next, lds + b_dec, SLOT, s0, c0, acc, u, pf[(k + 2) % D], vb0,
+                vb1, ops);
             __syncthreads();
             const int t = b_cur;
             b_cur = b_next;
@@ -679,6 +717,35 @@ __device__ __forceinline__ void run_wave(const CorrArgs &a, const Group &g, int 
     // workspace and the merge kernel, launched next on the same stream, adds
     // them: the kernel boundary orders the two, so no fence or counter is
     // needed and the additions spread over the whole GPU.
+    // Halves geometry: waves 6 and 7 (odd steps) hand their sums to waves 4
+    // and 5 (even steps, the same tiles and layout) through LDS, which is
+    // free after the loop's last barrier; only waves 4 and 5 write.
+    if (kSmall) {
+        int32_t *cb = (int32_t *)lds + (wave & 1) * (8 * 16 * 64);
+        auto each = [&](auto fn) {
+            int m = 0;
+#pragma unroll
+            for (int k = 0; k < TL::NQ; ++k) fn(acc.q[k], m++);
+#pragma unroll
+            for (int k = 0; k < TL::NO; ++k) {
+                fn(acc.re[k], m++);
+                fn(acc.im[k], m++);
+            }
+        };
+        if (kMma && wave >= 6)
+            each([&](v16i &x, int m) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) cb[(m * 16 + v) * 64 + lane] = x[v];
+            });
+        __syncthreads();
+        if (kMma && (wave == 4 || wave == 5))
+            each([&](v16i &x, int m) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) x[v] += cb[(m * 16 + v) * 64 + lane];
+            });
+        __syncthreads();
+        if (!(kMma && (wave == 4 || wave == 5))) return;
+    }
     constexpr int NT = TL::NT;
     int32_t *tbuf = (int32_t *)lds + wave * (32 * 33);  // staging buffers are free now
     const TileMap<SHAPE> map{g, s0, c0, a.N};
@@ -745,15 +812,15 @@ __device__ __forceinline__ int64_t xcd_local_index(int64_t b, int64_t total) {
 // One work item: tile group gid of channel f over time chunk `split`.
 // Every wave runs the same number of steps and barriers; the tile pattern is
 // fixed per group kind (blocks past N are staged as zeros).
-template <bool kAligned, bool kOverwrite>
+template <bool kAligned, bool kOverwrite, int KINDS = kAllKinds>
 __device__ __forceinline__ void run_item(const CorrArgs &a, int f, int gid, int split,
                                          uint8_t *lds, uint32_t *mwords) {
-    const Group g = make_group(a.nb, gid);
+    const Group g = make_group(a.nb, gid, a.halves);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    with_role(g, wave, [&](auto role, int s0, int c0) {
+    with_role<KINDS>(g, wave, [&](auto role, int s0, int c0) {
         using R = decltype(role);
-        run_wave<kAligned, kOverwrite, R::NSLOT, R::SHAPE, R::UPT>(a, g, f, gid, split, s0, c0,
-                                                                  lds, mwords);
+        run_wave<kAligned, kOverwrite, R::NSLOT, R::SHAPE, R::UPT, R::kMma, R::kSmall>(
+            a, g, f, gid, split, s0, c0, lds, mwords);
     });
 }
 
@@ -787,6 +854,7 @@ struct BatchInstance {
     int32_t N, F, T, B;
     int32_t nblk_mask, nb, groups, splits;
     int32_t steps_per_split, aligned;
+    int32_t halves, pad_;
     int64_t partial_base;  // first int32 of its partial tiles
 };
 
@@ -800,6 +868,9 @@ struct BatchItem {
 // the launch can be replayed from a graph.  Items are accumulated into their
 // instances' resident sums.  Instances must take the dword-load path
 // (N % 4 == 0, 4-byte aligned frame); the host runs others on their own.
+// A batch has one list of items per geometry, each drained by its own
+// launch of this kernel (KINDS = kSuperOnly or kHalvesOnly).
+template <int KINDS>
 __global__ __launch_bounds__(kThreads, 1) void batch_kernel(const BatchInstance *inst,
                                                             const BatchItem *items, int n_items,
                                                             int *queue,
@@ -840,7 +911,8 @@ __global__ __launch_bounds__(kThreads, 1) void batch_kernel(const BatchInstance 
         a.groups = u32(bi.groups);
         a.splits = u32(bi.splits);
         a.steps_per_split = u32(bi.steps_per_split);
-        run_item<true, false>(a, wf, wg, ws, lds, mwords);
+        a.halves = u32(bi.halves);
+        run_item<true, false, KINDS>(a, wf, wg, ws, lds, mwords);
     }
     if (threadIdx.x == 0) {
         int done = atomicAdd(&queue[1], 1);
@@ -861,6 +933,7 @@ struct MergeInst {
     int32_t *vis;
     int32_t *partials;
     int N, nb, groups, splits;
+    int halves, pad_;
     int64_t block_begin;  // first merge block of the instance (batch lists)
 };
 
@@ -923,7 +996,8 @@ __device__ __forceinline__ void merge_block(const MergeInst &m, int64_t b) {
     const int64_t key = b / kMergeBlocksPerGroup;
     const int wave = (int)(b / kTilesPerWave % kWaves);
     const int k = (int)(b % kTilesPerWave);
-    const Group g = make_group(m.nb, (int)(key % m.groups));
+    const Group g = make_group(m.nb, (int)(key % m.groups), m.halves);
+    if (g.small && wave != 4 && wave != 5) return;   // halves: waves 4 and 5 own the sums
     with_role(g, wave, [&](auto role, int s0, int c0) {
         merge_tile<decltype(role)::SHAPE>(m, g, key, wave, k, s0, c0);
     });

@@ -30,7 +30,7 @@ constexpr size_t kQueueBytes = 256;  // queue head and done counters, padded
 
 // sizes of a plan kept in a device slot
 struct SlotShape {
-    int n_inst = 0, n_items = 0, n_merges = 0;
+    int n_inst = 0, n_items = 0, n_small = 0, n_merges = 0;  // n_small: halves items
     int64_t merge_blocks = 0;
 };
 
@@ -50,6 +50,7 @@ struct xe_handle_s {
     hipEvent_t ring_done[kRingSlots];
     int ring_next;
     PlanSlot slots[kRingSlots + kPlanSlots];
+    int geometry;        // XE_GEOM_*: tile geometry of frames with N <= 128
     std::string last_error;
 };
 
@@ -128,7 +129,11 @@ size_t partial_bytes(int64_t keys, int splits) {
 
 // Returns false when time chunks are unavoidable but their partial sums do
 // not fit the workspace.
-bool fill_plan(int32_t N, int32_t F, int32_t T, int32_t n_cu, size_t ws_bytes,
+// the halves geometry for frames of at most 4 input blocks, unless the
+// caller asked for padded super-blocks
+int halves_of(int geometry) { return geometry == XE_GEOM_SUPER ? 0 : 1; }
+
+bool fill_plan(int32_t N, int32_t F, int32_t T, int32_t n_cu, size_t ws_bytes, int halves,
                xe_plan_info *p) {
     int nb = xe::ceil_div(N, xe::kBlk);
     int G = xe::groups_per_channel(nb);
@@ -156,7 +161,7 @@ bool fill_plan(int32_t N, int32_t F, int32_t T, int32_t n_cu, size_t ws_bytes,
     p->splits = splits;
     p->steps_per_split = sps;
     p->workgroups = keys * splits;
-    p->mfma_tiles = xe::tiles_per_channel(nb);
+    p->mfma_tiles = xe::tiles_per_channel(nb, halves);
     return splits == 1 || partial_bytes(keys, splits) <= ws_bytes;
 }
 
@@ -173,7 +178,8 @@ xe_status launch_corr(xe_handle h, const Scratch &ws, const uint8_t *packed, con
                       int32_t N, int32_t F, int32_t T, int32_t B, int32_t *vis, int64_t *count,
                       bool overwrite, hipStream_t stream) {
     xe_plan_info p;
-    if (!fill_plan(N, F, T, ws.n_cu, ws.bytes, &p))
+    const int halves = halves_of(h ? h->geometry : XE_GEOM_AUTO);
+    if (!fill_plan(N, F, T, ws.n_cu, ws.bytes, halves, &p))
         return fail(h, XE_ERR_WORKSPACE, "time chunks do not fit the workspace");
     xe::CorrArgs a;
     a.packed = packed;
@@ -191,6 +197,7 @@ xe_status launch_corr(xe_handle h, const Scratch &ws, const uint8_t *packed, con
     a.groups = p.groups;
     a.splits = p.splits;
     a.steps_per_split = p.steps_per_split;
+    a.halves = halves;
     if (p.workgroups > 0x7fffffff) return fail(h, XE_ERR_ARG, "too many workgroups");
     dim3 grid((unsigned)p.workgroups), block(xe::kThreads);
     bool al = aligned(packed, 4) && (N % 4 == 0);
@@ -221,6 +228,7 @@ xe_status launch_corr(xe_handle h, const Scratch &ws, const uint8_t *packed, con
         m.nb = p.blocks;
         m.groups = p.groups;
         m.splits = p.splits;
+        m.halves = halves;
         m.block_begin = 0;
         const int64_t blocks = (int64_t)F * p.groups * xe::kMergeBlocksPerGroup;
         if (blocks + F > 0x7fffffff) return fail(h, XE_ERR_ARG, "too many merge blocks");
@@ -255,7 +263,8 @@ void release_device_memory(xe_handle h) {
 
 struct BatchPlan {
     std::vector<xe::BatchInstance> inst;
-    std::vector<xe::BatchItem> items;
+    std::vector<xe::BatchItem> items;        // super-block groups
+    std::vector<xe::BatchItem> small_items;  // halves-geometry groups
     std::vector<xe_instance> unaligned;
     std::vector<xe::MergeInst> merges;  // chunked instances, for the merge pass
     std::vector<int64_t> merge_base;    // their first partial value in the workspace
@@ -266,7 +275,8 @@ struct BatchPlan {
 
 size_t plan_bytes(const BatchPlan &p) {
     return kQueueBytes + p.inst.size() * sizeof(xe::BatchInstance) +
-           p.items.size() * sizeof(xe::BatchItem) + p.merges.size() * sizeof(xe::MergeInst);
+           (p.items.size() + p.small_items.size()) * sizeof(xe::BatchItem) +
+           p.merges.size() * sizeof(xe::MergeInst);
 }
 
 // Work items of a batch: every (instance, channel, group, time chunk), with
@@ -276,6 +286,7 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
                       int32_t chunk_steps, size_t ws_bytes, BatchPlan *plan) {
     if (n_inst < 0 || (n_inst > 0 && !inst)) return fail(h, XE_ERR_ARG, "bad batch arguments");
     if (chunk_steps < 0) return fail(h, XE_ERR_ARG, "chunk_steps must be >= 0");
+    const int halves = halves_of(h->geometry);
     int64_t work = 0;
     for (int32_t k = 0; k < n_inst; ++k) {
         const xe_instance &x = inst[k];
@@ -311,7 +322,7 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
         int64_t steps;
         xe::BatchItem item;
     };
-    std::vector<Cost> costs;
+    std::vector<Cost> costs, small_costs;
     for (int32_t k = 0; k < n_inst; ++k) {
         const xe_instance &x = inst[k];
         if (!aligned(x.packed, 4) || x.N % 4 != 0) {
@@ -341,6 +352,8 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
         b.splits = splits;
         b.steps_per_split = sps;
         b.aligned = 1;
+        b.halves = halves;
+        b.pad_ = 0;
         b.partial_base = plan->partials;
         if (splits > 1) {
             xe::MergeInst m;
@@ -350,6 +363,8 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
             m.nb = nb;
             m.groups = G;
             m.splits = splits;
+            m.halves = halves;
+            m.pad_ = 0;
             m.block_begin = plan->merge_blocks;
             plan->merges.push_back(m);
             plan->merge_base.push_back(plan->partials);
@@ -358,17 +373,22 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
         }
         const int idx = (int)plan->inst.size();
         plan->inst.push_back(b);
+        // halves-geometry items go to their own list and launch
+        std::vector<Cost> &to = xe::use_halves(halves, nb) ? small_costs : costs;
         for (int f = 0; f < x.F; ++f)
             for (int gid = 0; gid < G; ++gid)
                 for (int sp = 0; sp < splits; ++sp) {
                     int64_t len = std::min<int64_t>(sps, steps - (int64_t)sp * sps);
-                    costs.push_back({len, {idx, f, gid, sp}});
+                    to.push_back({len, {idx, f, gid, sp}});
                 }
     }
-    std::stable_sort(costs.begin(), costs.end(),
-                     [](const Cost &a, const Cost &b) { return a.steps > b.steps; });
+    auto longest_first = [](const Cost &a, const Cost &b) { return a.steps > b.steps; };
+    std::stable_sort(costs.begin(), costs.end(), longest_first);
+    std::stable_sort(small_costs.begin(), small_costs.end(), longest_first);
     plan->items.reserve(costs.size());
     for (const Cost &c : costs) plan->items.push_back(c.item);
+    plan->small_items.reserve(small_costs.size());
+    for (const Cost &c : small_costs) plan->small_items.push_back(c.item);
     if ((size_t)plan->partials * sizeof(int32_t) > ws_bytes)
         return fail(h, XE_ERR_WORKSPACE, "batch partial sums do not fit the workspace");
     if (plan->merge_blocks > 0x7fffffff) return fail(h, XE_ERR_ARG, "too many merge blocks");
@@ -376,8 +396,9 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
     return XE_OK;
 }
 
-// Slot layout: [queue][instances][items][merge list]; the merge list's
-// partial pointers are filled in from the handle's workspace.
+// Slot layout: [queues][instances][items][halves items][merge list]; the
+// queue area holds two (head, done) pairs, one per item list; the merge
+// list's partial pointers are filled in from the handle's workspace.
 void write_plan(const BatchPlan &p, int32_t *workspace, char *dst) {
     memset(dst, 0, kQueueBytes);
     char *q = dst + kQueueBytes;
@@ -385,6 +406,8 @@ void write_plan(const BatchPlan &p, int32_t *workspace, char *dst) {
     q += p.inst.size() * sizeof(xe::BatchInstance);
     memcpy(q, p.items.data(), p.items.size() * sizeof(xe::BatchItem));
     q += p.items.size() * sizeof(xe::BatchItem);
+    memcpy(q, p.small_items.data(), p.small_items.size() * sizeof(xe::BatchItem));
+    q += p.small_items.size() * sizeof(xe::BatchItem);
     for (size_t k = 0; k < p.merges.size(); ++k) {
         xe::MergeInst m = p.merges[k];
         m.partials = workspace + p.merge_base[k];
@@ -397,22 +420,29 @@ SlotShape shape_of(const BatchPlan &p) {
     SlotShape sh;
     sh.n_inst = (int)p.inst.size();
     sh.n_items = (int)p.items.size();
+    sh.n_small = (int)p.small_items.size();
     sh.n_merges = (int)p.merges.size();
     sh.merge_blocks = p.merge_blocks;
     return sh;
 }
 
 xe_status launch_batch(xe_handle h, int slot, const SlotShape &sh, hipStream_t stream) {
-    if (sh.n_items == 0) return XE_OK;
+    if (sh.n_items + sh.n_small == 0) return XE_OK;
     char *base = (char *)h->plan_area + (size_t)slot * kSlotBytes;
     const xe::BatchInstance *bi = (const xe::BatchInstance *)(base + kQueueBytes);
     const xe::BatchItem *items = (const xe::BatchItem *)(base + kQueueBytes +
                                                            sh.n_inst * sizeof(xe::BatchInstance));
-    const xe::MergeInst *merges =
-        (const xe::MergeInst *)((const char *)items + sh.n_items * sizeof(xe::BatchItem));
-    int grid = std::min(h->n_cu, sh.n_items);
-    hipLaunchKernelGGL(xe::batch_kernel, dim3(grid), dim3(xe::kThreads), 0, stream, bi, items,
-                       sh.n_items, (int *)base, (int32_t *)h->workspace);
+    const xe::BatchItem *small = items + sh.n_items;
+    const xe::MergeInst *merges = (const xe::MergeInst *)(small + sh.n_small);
+    int *queues = (int *)base;   // [0, 1]: super-block items, [2, 3]: halves items
+    if (sh.n_items > 0)
+        hipLaunchKernelGGL(xe::batch_kernel<xe::kSuperOnly>, dim3(std::min(h->n_cu, sh.n_items)),
+                           dim3(xe::kThreads), 0, stream, bi, items, sh.n_items, queues,
+                           (int32_t *)h->workspace);
+    if (sh.n_small > 0)
+        hipLaunchKernelGGL(xe::batch_kernel<xe::kHalvesOnly>,
+                           dim3(std::min(h->n_cu, sh.n_small)), dim3(xe::kThreads), 0, stream, bi,
+                           small, sh.n_small, queues + 2, (int32_t *)h->workspace);
     hipLaunchKernelGGL(xe::count_list_kernel, dim3((unsigned)sh.n_inst),
                        dim3(64 * xe::kCountWaves), 0, stream, bi, sh.n_inst);
     hipError_t e = hipGetLastError();
@@ -492,6 +522,7 @@ xe_status xe_create(xe_handle *out, int32_t hip_device, size_t workspace_bytes) 
     h->plan_area = nullptr;
     h->staging = nullptr;
     h->ring_next = 0;
+    h->geometry = XE_GEOM_AUTO;
     for (int k = 0; k < kRingSlots; ++k) h->ring_done[k] = nullptr;
     if (hip_device == XE_DEVICE_NONE) {
         *out = h;
@@ -571,13 +602,22 @@ const char *xe_status_string(xe_status s) {
 
 const char *xe_last_error(xe_handle h) { return h ? h->last_error.c_str() : ""; }
 
+xe_status xe_set_geometry(xe_handle h, int32_t geometry) {
+    if (!h) return XE_ERR_ARG;
+    if (geometry != XE_GEOM_AUTO && geometry != XE_GEOM_SUPER && geometry != XE_GEOM_HALVES)
+        return fail(h, XE_ERR_ARG, "unknown geometry");
+    h->geometry = geometry;
+    return XE_OK;
+}
+
 xe_status xe_plan_query(int32_t N, int32_t F, int32_t T, int32_t B, int32_t n_cu,
                         xe_plan_info *info) {
     if (!info) return XE_ERR_ARG;
     xe_status s = check_shape(nullptr, N, F, T, B);
     if (s != XE_OK) return s;
     if (n_cu < 1) return XE_ERR_ARG;
-    if (!fill_plan(N, F, T, n_cu, kDefaultWorkspace, info)) return XE_ERR_WORKSPACE;
+    if (!fill_plan(N, F, T, n_cu, kDefaultWorkspace, halves_of(XE_GEOM_AUTO), info))
+        return XE_ERR_WORKSPACE;
     return XE_OK;
 }
 
@@ -834,7 +874,7 @@ xe_status xe_accumulate_batch(xe_handle h, const xe_instance *inst, int32_t n_in
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, XE_ERR_HIP, "hipSetDevice failed");
     hipStream_t st = (hipStream_t)stream;
-    if (!plan.items.empty()) {
+    if (!plan.items.empty() || !plan.small_items.empty()) {
         // the ring slot (and its pinned staging copy) is free once the
         // launch that last used it has finished
         const int slot = h->ring_next;
@@ -924,7 +964,7 @@ xe_status xe_batch_query(const xe_instance *inst, int32_t n_inst, int32_t n_cu,
     probe.device = XE_DEVICE_NONE;
     xe_status s = build_batch(&probe, inst, n_inst, n_cu, chunk_steps, kDefaultWorkspace, &plan);
     if (s != XE_OK) return s;
-    info->items = (int64_t)plan.items.size();
+    info->items = (int64_t)(plan.items.size() + plan.small_items.size());
     info->instances = (int32_t)plan.inst.size();
     info->unaligned = (int32_t)plan.unaligned.size();
     info->chunk_steps = plan.chunk_steps;

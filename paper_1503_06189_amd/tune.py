@@ -1,12 +1,16 @@
-"""Autotuner for batched launches: picks the time-chunk length of a batch.
+"""Autotuner for batched launches: picks the tile geometry and the
+time-chunk length of a batch.
 
 A batch's work list cuts every (instance, channel, tile group) into time
 chunks; short chunks balance the persistent grid but cost a partial-sum
 round trip through HBM each, long chunks leave compute units idle at the
-tail.  The tuner times the feasible candidates on scratch accumulators of
-the batch's own shapes (the caller's sums are never touched), keeps the
-fastest, and caches the choice in a JSON file keyed by the device
-architecture and the batch's shape signature.
+tail.  Instances with N <= 128 run either as padded 256-input super-blocks
+or in the halves geometry (the 10 tiles of a 4-block triangle over pairs of
+32-sample steps).  The tuner times every feasible (geometry, chunk length)
+candidate on scratch accumulators of the batch's own shapes (the caller's
+sums are never touched), keeps the fastest, and caches the choice in a
+JSON file keyed by the device architecture and the batch's shape
+signature.
 
 Cache file: ``$XE_TUNE_CACHE`` if set, else ``~/.cache/xengine/tune.json``.
 """
@@ -17,11 +21,24 @@ import hashlib
 import json
 import os
 import threading
+from dataclasses import dataclass
 from typing import Dict, List, Optional, Sequence, Tuple
 
 from . import xengine
 
 _lock = threading.Lock()
+
+#: cache entries written by this version (older entries carry no geometry)
+CACHE_VERSION = 2
+
+
+@dataclass(frozen=True)
+class Choice:
+    """A batch's tuned launch: chunk length in 32-sample steps and the tile
+    geometry of its N <= 128 instances ("super" or "halves"; "auto" when
+    the batch has none)."""
+    chunk_steps: int
+    geometry: str
 
 
 def cache_path() -> str:
@@ -76,45 +93,52 @@ def candidates(shapes: Sequence[Tuple[int, int, int, int]], n_cu: int) -> List[i
     return out
 
 
+def geometries(shapes: Sequence[Tuple[int, int, int, int]]) -> List[str]:
+    """Tile geometries worth timing: both when an instance has N <= 128."""
+    return ["super", "halves"] if any(n <= 128 for n, _, _, _ in shapes) else ["auto"]
+
+
 def tune(items: Sequence[Tuple], handle: Optional[xengine.Handle] = None,
-         reps: int = 5, use_cache: bool = True, path: Optional[str] = None) -> int:
-    """Best chunk length (32-sample steps) for a batch of
-    (packed, mask, B, vis, count) items; runs on scratch accumulators."""
+         reps: int = 5, use_cache: bool = True, path: Optional[str] = None) -> Choice:
+    """Best (chunk length, geometry) for a batch of (packed, mask, B, vis,
+    count) items; runs on scratch accumulators."""
     import torch
     if not items:
-        return 0
+        return Choice(0, "auto")
     dev = items[0][0].device
     shapes = [(int(p.shape[2]), int(p.shape[1]), int(p.shape[0]), int(B))
               for p, m, B, v, c in items]
     key = f"{_arch(dev.index)}|{signature(shapes)}"
     if use_cache:
         hit = load_cache(path).get(key)
-        if hit is not None:
-            return int(hit["chunk_steps"])
+        if hit is not None and hit.get("version") == CACHE_VERSION:
+            return Choice(int(hit["chunk_steps"]), str(hit["geometry"]))
     n_cu = torch.cuda.get_device_properties(dev.index).multi_processor_count
     h = handle or xengine.default_handle(dev.index)
     scratch = [(p, m, B, torch.zeros_like(v), torch.zeros_like(c)) for p, m, B, v, c in items]
     timings = {}
     stream = torch.cuda.current_stream(dev)
-    for cs in candidates(shapes, n_cu):
-        for _, _, _, v, _ in scratch:     # every candidate integrates afresh
-            xengine.reset_integration(v)
-        plan = xengine.BatchPlan(scratch, chunk_steps=cs, handle=h)
-        try:
-            plan.run(stream)   # warm-up
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                plan.run(stream)
-            e1.record(stream)
-            e1.synchronize()
-            timings[cs] = e0.elapsed_time(e1) / reps
-        finally:
-            plan.release()
+    for geom in geometries(shapes):
+        for cs in candidates(shapes, n_cu):
+            for _, _, _, v, _ in scratch:     # every candidate integrates afresh
+                xengine.reset_integration(v)
+            plan = xengine.BatchPlan(scratch, chunk_steps=cs, handle=h, geometry=geom)
+            try:
+                plan.run(stream)   # warm-up
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    plan.run(stream)
+                e1.record(stream)
+                e1.synchronize()
+                timings[(geom, cs)] = e0.elapsed_time(e1) / reps
+            finally:
+                plan.release()
     del scratch
-    best = min(timings, key=timings.get)
-    _store(key, {"chunk_steps": best, "ms": timings[best],
-                 "timings_ms": {str(k): round(v, 5) for k, v in timings.items()},
+    geom, cs = min(timings, key=timings.get)
+    _store(key, {"version": CACHE_VERSION, "chunk_steps": cs, "geometry": geom,
+                 "ms": timings[(geom, cs)],
+                 "timings_ms": {f"{g}/{c}": round(v, 5) for (g, c), v in timings.items()},
                  "instances": len(shapes)}, path)
-    return best
+    return Choice(cs, geom)

@@ -29,9 +29,14 @@ XE_ERR_NO_DEVICE = -7
 XE_MAX_N = 4096
 XE_MAX_SAMPLES = 16777215
 XE_DEVICE_NONE = -1
+XE_GEOM_AUTO = 0
+XE_GEOM_SUPER = 1
+XE_GEOM_HALVES = 2
+#: tile geometries of frames with N <= 128, by name
+GEOMETRIES = {"auto": XE_GEOM_AUTO, "super": XE_GEOM_SUPER, "halves": XE_GEOM_HALVES}
 
 #: every function the header declares
-EXPORTS = ("xe_create", "xe_destroy", "xe_status_string", "xe_last_error",
+EXPORTS = ("xe_create", "xe_destroy", "xe_status_string", "xe_last_error", "xe_set_geometry",
            "xe_correlate_frame", "xe_accumulate", "xe_normalize",
            "xe_accumulate_batch", "xe_batch_plan", "xe_batch_run", "xe_batch_release",
            "xe_batch_query", "xe_plan_query",
@@ -168,6 +173,8 @@ def lib() -> ctypes.CDLL:
             L.xe_status_string.argtypes = [i32]
             L.xe_last_error.restype = ctypes.c_char_p
             L.xe_last_error.argtypes = [vp]
+            L.xe_set_geometry.restype = i32
+            L.xe_set_geometry.argtypes = [vp, i32]
             for name in ("xe_correlate_frame", "xe_accumulate"):
                 fn = getattr(L, name)
                 fn.restype = i32
@@ -230,6 +237,7 @@ class Handle:
         if s != XE_OK:
             raise XEngineError(s, status_string(s))
         self._h = h
+        self.geometry = XE_GEOM_AUTO
 
     @property
     def ptr(self):
@@ -239,6 +247,13 @@ class Handle:
         if s != XE_OK:
             msg = lib().xe_last_error(self._h).decode() or status_string(s)
             raise XEngineError(s, msg)
+
+    def set_geometry(self, geometry) -> None:
+        """Tile geometry of frames with N <= 128 for later calls and plans:
+        "auto", "super" or "halves", or an XE_GEOM_* value."""
+        g = GEOMETRIES[geometry] if isinstance(geometry, str) else int(geometry)
+        self.check(lib().xe_set_geometry(self._h, g))
+        self.geometry = g
 
     def close(self) -> None:
         if self._h:
@@ -570,13 +585,24 @@ class BatchPlan:
     tensors are referenced here so they outlive the plan."""
 
     def __init__(self, items: Sequence[Tuple], chunk_steps: int = 0,
-                 handle: Optional[Handle] = None):
+                 handle: Optional[Handle] = None, geometry=None):
         arr, dev = _instances(items)
         self.handle = handle or default_handle(dev)
         self.items = list(items)
         pid = ctypes.c_int32(-1)
-        self.handle.check(lib().xe_batch_plan(self.handle.ptr, arr, len(items), chunk_steps,
-                                              ctypes.byref(pid)))
+        # the plan keeps the tile geometry it is built with; the handle's
+        # own setting is restored afterwards
+        before = self.handle.geometry
+        if geometry is not None:
+            self.handle.set_geometry(geometry)
+        try:
+            self.handle.check(lib().xe_batch_plan(self.handle.ptr, arr, len(items), chunk_steps,
+                                                  ctypes.byref(pid)))
+        finally:
+            if geometry is not None:
+                self.handle.set_geometry(before)
+        self.geometry = self.handle.geometry if geometry is None else (
+            GEOMETRIES[geometry] if isinstance(geometry, str) else int(geometry))
         self.plan_id = pid.value
 
     def run(self, stream=None) -> None:

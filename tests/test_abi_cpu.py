@@ -228,6 +228,41 @@ def test_tile_groups_cover_the_triangle_once():
         assert sorted(tiles) == want, nb
 
 
+def test_halves_geometry_model():
+    """Host model of the halves geometry (N <= 128): slots 0..3 hold blocks
+    0..3 at the even 32-sample step of a pair, slots 4..7 the same blocks at
+    the odd one.  Waves 4..7 keep their triangle roles: waves 4, 5 cover the
+    10 tiles of the 4-block triangle over the even steps and waves 6, 7 over
+    the odd ones, each tile exactly once per step, never pairing slots of
+    different steps; the rectangle waves (0..3) would pair different steps,
+    so they stage only."""
+    def tri(w):
+        if w % 2 == 0:
+            b = 2 * (w - 4)
+            return [(b, b), (b + 1, b + 1)] + [(b, b + c) for c in (1, 2, 3)]
+        b = 2 * (w - 5)
+        return [(b + 2, b + 2), (b + 3, b + 3), (b + 1, b + 2), (b + 1, b + 3), (b + 2, b + 3)]
+    block, step = (lambda s: s % 4), (lambda s: s // 4)
+    want = sorted((i, j) for i in range(4) for j in range(i, 4))
+    for parity, waves in ((0, (4, 5)), (1, (6, 7))):
+        tiles = []
+        for w in waves:
+            for r, c in tri(w):
+                assert step(r) == step(c) == parity
+                tiles.append((block(r), block(c)))
+        assert sorted(tiles) == want
+    for w in range(4):                       # rectangle: row slot w x slots 4..7
+        assert all(step(w) != step(4 + c) for c in range(4))
+
+
+def test_set_geometry_checks(L, h):
+    for g in (xe.XE_GEOM_AUTO, xe.XE_GEOM_SUPER, xe.XE_GEOM_HALVES):
+        assert L.xe_set_geometry(h, g) == xe.XE_OK
+    assert L.xe_set_geometry(h, 3) == xe.XE_ERR_ARG
+    assert L.xe_set_geometry(h, -1) == xe.XE_ERR_ARG
+    assert L.xe_set_geometry(None, 0) == xe.XE_ERR_ARG
+
+
 def test_flag_checks(L, h):
     def acc(flags=0x1000, mask=None, N=40, F=2, T=64, B=16, d=0x200000, hh=h):
         return L.xe_flag_accumulate(hh, ctypes.c_void_p(flags), ctypes.c_void_p(mask), N, F,

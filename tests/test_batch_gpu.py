@@ -124,19 +124,25 @@ def full_batch(orc):
 
 
 def test_batch_full_size_matches_oracle(xe, orc, full_batch):
-    """All 128 instances in one persistent launch, chunk length from the
-    autotuner's search space as the benchmark runs it, replayed from a
+    """All 128 instances in one persistent launch, geometry and chunk length
+    from the autotuner's search space as the benchmark runs it (the cache
+    entry holds both, and both geometries were timed), replayed from a
     captured graph: every instance's sums equal the oracle's."""
     frs, want = full_batch
     insts = [Inst(xe, f) for f in frs]
     from paper_1503_06189_amd import tune
     import tempfile
     with tempfile.TemporaryDirectory() as d:
-        cs = tune.tune([i.item() for i in insts], path=d + "/tune.json", reps=2)
-    _say(f"tuned chunk length {cs} steps")
+        choice = tune.tune([i.item() for i in insts], path=d + "/tune.json", reps=2)
+        cached = tune.load_cache(d + "/tune.json")
+    _say(f"tuned chunk length {choice.chunk_steps} steps, geometry {choice.geometry}")
+    (entry,) = cached.values()
+    assert entry["geometry"] == choice.geometry and entry["chunk_steps"] == choice.chunk_steps
+    assert {k.split("/")[0] for k in entry["timings_ms"]} == {"super", "halves"}
     for ins in insts:
         ins.zero()
-    plan = xe.BatchPlan([i.item() for i in insts], chunk_steps=cs)
+    plan = xe.BatchPlan([i.item() for i in insts], chunk_steps=choice.chunk_steps,
+                        geometry=choice.geometry)
     try:
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()

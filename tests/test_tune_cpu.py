@@ -31,3 +31,18 @@ def test_candidates_are_feasible():
     assert auto in c and (1 << 18) in c and c == sorted(c)
     for cs in c:
         xengine.batch_query(shapes, n_cu=256, chunk_steps=cs)   # fits the workspace
+
+
+def test_geometries_only_for_small_instances():
+    assert tune.geometries([(64, 1, 1024, 256), (512, 1, 4096, 256)]) == ["super", "halves"]
+    assert tune.geometries([(129, 1, 1024, 256), (512, 1, 4096, 256)]) == ["auto"]
+
+
+def test_old_cache_entries_are_not_used(tmp_path):
+    """Entries without a geometry (an older cache) do not count as hits:
+    the choice returned always carries a geometry."""
+    path = str(tmp_path / "t.json")
+    tune._store("k", {"chunk_steps": 300, "ms": 1.0}, path)
+    assert tune.load_cache(path)["k"].get("version") != tune.CACHE_VERSION
+    c = tune.Choice(300, "halves")
+    assert (c.chunk_steps, c.geometry) == (300, "halves")
