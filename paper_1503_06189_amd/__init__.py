@@ -4,7 +4,8 @@ Submodules:
   xengine  -- ctypes binding of libxengine.so (the HIP path)
   synth    -- seeded synthetic frames and loss masks
   metrics  -- rate and work definitions for reports
-  tune     -- autotuner of batched persistent launches (cached per device)
+  tune     -- autotuner of batched persistent launches: tile geometry and
+              time-chunk length, cached per device
   serve    -- streaming server: admission by HBM budget, continuous batching
 """
 

@@ -32,6 +32,7 @@ from __future__ import annotations
 import collections
 import dataclasses
 import queue
+import sys
 import threading
 import time
 from typing import Callable, Deque, Dict, List, Optional
@@ -60,15 +61,29 @@ class StreamConfig:
 class Frame:
     stream_id: int
     seq: int                     # sequence number of the frame in its stream
-    packed: "object"             # pinned uint8 [T][F][N] host tensor
+    packed: "object"             # pinned uint8 [T][F][N] host tensor (or in HBM)
     mask: "object"               # pinned uint8 [F][nblk] host tensor or None
     t_arrival: float             # time.perf_counter() at arrival
     # set by the server
-    dev_packed: "object" = None
-    dev_mask: "object" = None
-    ev_copied: "object" = None
-    nbytes: int = 0
+    slices: int = 0              # time slices the frame is copied and integrated in
+    copied: int = 0              # slices whose copy has been issued
+    launched: int = 0            # slices launched
+    ev_copy_start: "object" = None
+    ev_copied: "object" = None   # copy of the last slice done
+    t_copy_issue: float = 0.0    # host time the first slice's copy was issued
+    done: int = 0                # slices whose batch has finished
     t_done: float = 0.0
+
+
+@dataclasses.dataclass
+class _Slice:
+    frame: Frame
+    t0: int
+    t1: int
+    packed: "object"             # device uint8 [t1 - t0][F][N]
+    mask: "object"               # device uint8 [F][ceil((t1 - t0) / B)] or None
+    ev_copied: "object"          # None: nothing to wait for
+    slot: int = -1               # pool slot, released when the batch is done
 
 
 @dataclasses.dataclass
@@ -86,7 +101,8 @@ class IntegrationResult:
 
 
 class _Stream:
-    def __init__(self, cfg: StreamConfig, device, pinned_results: bool = True):
+    def __init__(self, cfg: StreamConfig, device, slice_samples: int,
+                 pinned_results: bool = True):
         import torch
         self.cfg = cfg
         N, F = cfg.N, cfg.F
@@ -100,15 +116,19 @@ class _Stream:
                      for _ in range(2)]
         self.ev_d2h = [None, None]   # copy-out of buffer k finished
         self.host_busy = [False, False]  # host copy k not yet taken
+        self.host_free = [threading.Event(), threading.Event()]
+        for e in self.host_free:
+            e.set()
         self.cur = 0
         self.frames_in = 0           # frames launched into the current integration
         self.seq_first = -1          # ... and the sequence numbers they span
         self.seq_last = -1
         self.window = -1             # aligned: window of the current integration
         self.index = 0
-        self.pending: Deque[Frame] = collections.deque()   # admitted, not launched
-        self.waiting: Deque[Frame] = collections.deque()   # arrived, not admitted
-        self.resident_bytes = 2 * (2 * F * P * 8 + F * 8)
+        self.slice_samples = slice_samples
+        self.pending: Deque[_Slice] = collections.deque()  # copied or copying, not launched
+        self.waiting: Deque[Frame] = collections.deque()   # arrived, slices left to copy
+        self.resident_bytes = self.resident_bytes_for(cfg)
 
     @staticmethod
     def resident_bytes_for(cfg: StreamConfig) -> int:
@@ -116,46 +136,127 @@ class _Stream:
         return 2 * (2 * cfg.F * P * 8 + cfg.F * 8)
 
 
-def frame_bytes(cfg: StreamConfig) -> int:
-    nblk = (cfg.T + cfg.B - 1) // cfg.B
-    return cfg.T * cfg.F * cfg.N + cfg.F * nblk
+class SlotPool:
+    """Device frame buffers carved once, at start-up, out of the HBM budget
+    (the counterpart of the ring buffers of Sec. II-A): ``n`` slots of
+    ``slot_bytes`` for a time slice of packed samples, each with a small
+    region for the slice's loss mask and a pinned host staging area for
+    that mask.  Nothing is allocated or freed in steady state."""
+
+    MASK_BYTES = 4096
+
+    def __init__(self, torch, device, n: int, slot_bytes: int):
+        self.n = n
+        self.slot_bytes = slot_bytes
+        self.data = torch.empty(n * slot_bytes, dtype=torch.uint8, device=device)
+        self.masks = torch.empty(n * self.MASK_BYTES, dtype=torch.uint8, device=device)
+        self.host_masks = torch.empty(n * self.MASK_BYTES, dtype=torch.uint8, pin_memory=True)
+        self.free: List[int] = list(range(n - 1, -1, -1))
+
+    @property
+    def bytes(self) -> int:
+        return self.n * (self.slot_bytes + self.MASK_BYTES)
+
+    def take(self) -> int:
+        return self.free.pop() if self.free else -1
+
+    def give(self, k: int) -> None:
+        self.free.append(k)
+
+    def packed(self, k: int, shape):
+        n = shape[0] * shape[1] * shape[2]
+        return self.data[k * self.slot_bytes:k * self.slot_bytes + n].view(shape)
+
+    def mask(self, k: int, shape, host: bool = False):
+        n = shape[0] * shape[1]
+        buf = self.host_masks if host else self.masks
+        return buf[k * self.MASK_BYTES:k * self.MASK_BYTES + n].view(shape)
+
+
+def slice_samples_for(cfg: StreamConfig, slot_bytes: int, want: Optional[int] = None) -> int:
+    """Samples per time slice of a stream's frames: at most ``want`` (default:
+    the whole frame) and what fits one slot, a multiple of the loss-mask
+    block so that every slice's mask is whole blocks of the frame's."""
+    per_sample = cfg.F * cfg.N
+    fit = slot_bytes // per_sample // cfg.B * cfg.B
+    if fit < 1:
+        raise ValueError(f"stream {cfg.stream_id}: one {cfg.B}-sample mask block "
+                         f"({cfg.B * per_sample} B) does not fit a {slot_bytes} B slot")
+    s = min(cfg.T, fit)
+    if want is not None:
+        s = min(s, max(cfg.B, want // cfg.B * cfg.B))
+    if cfg.F * ((s + cfg.B - 1) // cfg.B) > SlotPool.MASK_BYTES:
+        raise ValueError(f"stream {cfg.stream_id}: a slice's loss mask exceeds "
+                         f"{SlotPool.MASK_BYTES} B; use shorter slices")
+    return s
 
 
 class StreamServer:
-    """Admission, batching and integration of frames from many streams."""
+    """Admission, batching and integration of frames from many streams.
+
+    Host frames are copied in time slices of at most ``slice_samples``
+    samples (default: whole frames, as far as a slot holds them) into slots
+    of a device pool carved out of ``hbm_budget`` at start-up
+    (``pool_bytes``, default half the budget; the rest holds the streams'
+    resident accumulators).  A slice is accumulated as soon as its copy has
+    landed: one batched launch takes the oldest landed slice of every
+    stream, so a frame's compute overlaps the copy of its later slices and
+    a large frame does not hold the GPU until it has crossed the host link
+    whole.  Copies are issued oldest frame first, as slots free up."""
 
     def __init__(self, hbm_budget: int, device: int = 0, max_inflight: int = 2,
                  handle: Optional[xengine.Handle] = None,
-                 on_result: Optional[Callable[[IntegrationResult], None]] = None):
+                 on_result: Optional[Callable[[IntegrationResult], None]] = None,
+                 slot_bytes: int = 32 << 20, pool_bytes: Optional[int] = None,
+                 slice_samples: Optional[int] = None):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
         self.budget = int(hbm_budget)
-        self.used = 0
         self.max_inflight = max_inflight
         self.h = handle or xengine.default_handle(device)
         self.copy_stream = torch.cuda.Stream(self.device)
         self.compute_stream = torch.cuda.Stream(self.device)
         self.d2h_stream = torch.cuda.Stream(self.device)
+        pool_bytes = self.budget // 2 if pool_bytes is None else int(pool_bytes)
+        n_slots = pool_bytes // (slot_bytes + SlotPool.MASK_BYTES)
+        if n_slots < 1:
+            raise MemoryError(f"a {pool_bytes} B pool holds no {slot_bytes} B slot")
+        self.pool = SlotPool(torch, self.device, n_slots, slot_bytes)
+        self.used = self.pool.bytes
+        self.slice_want = slice_samples
         self.streams: Dict[int, _Stream] = {}
         self.arrivals: "queue.Queue[Frame]" = queue.Queue()
-        self.inflight: Deque[tuple] = collections.deque()   # (event, frames)
-        self.outgoing: Deque[tuple] = collections.deque()   # (event, stream, k, index, frames)
+        self.inflight: Deque[tuple] = collections.deque()   # (event, slices)
+        # finished integrations are handed to a delivery thread, which waits
+        # for their copy-out and copies them out of the pinned buffers, so
+        # that the scheduling loop never copies a result (tens of MB)
+        self._out_q: "queue.Queue" = queue.Queue()
+        self._out_pending = 0
+        self._out_lock = threading.Lock()
+        self._deliverer = threading.Thread(target=self._deliver, daemon=True)
+        self._deliverer.start()
         self.results: Dict[int, List[IntegrationResult]] = collections.defaultdict(list)
         self.on_result = on_result
         self.latencies: List[float] = []
+        self.breakdown: List[tuple] = []   # per frame: (wait, copy, finish) seconds
+        self.done_frames: List[tuple] = []  # per frame: (stream, seq, arrival time)
         self.bytes_done = 0
         self.samples_done = 0
         self.frames_done = 0
         self.batches = 0
         self.batch_sizes: List[int] = []
-        self.max_used = 0
+        self.max_used = self.used
         self.admission_waits = 0
-        # host clock <-> GPU clock: an event recorded and waited for now
-        self._ev_ref = torch.cuda.Event(enable_timing=True)
-        self._ev_ref.record(self.compute_stream)
-        self._ev_ref.synchronize()
-        self._t_ref = time.perf_counter()
+        # host clock <-> GPU clock: an event recorded and waited for now,
+        # re-anchored every 20 ms while serving (the two clocks drift apart
+        # by parts per thousand over seconds)
+        ev_ref = torch.cuda.Event(enable_timing=True)
+        ev_ref.record(self.compute_stream)
+        ev_ref.synchronize()
+        self._ref = (ev_ref, time.perf_counter())   # one attribute: replaced whole
+        self._anchor = None          # anchor event in flight
+        self._anchor_period = 0.02
 
     # -- streams ----------------------------------------------------------
 
@@ -163,14 +264,15 @@ class StreamServer:
         if cfg.stream_id in self.streams:
             raise ValueError(f"stream {cfg.stream_id} already open")
         need = _Stream.resident_bytes_for(cfg)
-        if need + frame_bytes(cfg) > self.budget - self.used:
+        if need > self.budget - self.used:
             raise MemoryError(
-                f"stream {cfg.stream_id}: accumulators ({need} B) plus one frame do not fit "
-                f"the HBM budget ({self.budget - self.used} B free)")
+                f"stream {cfg.stream_id}: accumulators ({need} B) do not fit the HBM "
+                f"budget ({self.budget - self.used} B free beside the frame pool)")
+        s_len = slice_samples_for(cfg, self.pool.slot_bytes, self.slice_want)
         self.used += need
         self.max_used = max(self.max_used, self.used)
         with self.torch.cuda.stream(self.compute_stream):
-            self.streams[cfg.stream_id] = _Stream(cfg, self.device)
+            self.streams[cfg.stream_id] = _Stream(cfg, self.device, s_len)
 
     def close(self, stream_id: int) -> None:
         """Forget a stream whose frames have all been integrated."""
@@ -192,7 +294,29 @@ class StreamServer:
     # -- scheduling ---------------------------------------------------------
 
     def _gpu_time(self, ev) -> float:
-        return self._t_ref + self._ev_ref.elapsed_time(ev) / 1e3
+        ev_ref, t_ref = self._ref
+        return t_ref + ev_ref.elapsed_time(ev) / 1e3
+
+    def _reanchor(self) -> None:
+        """Move the clock anchor to a fresh event on a stream with no
+        queued work, taking the host time when the host sees it done."""
+        now = time.perf_counter()
+        if self._anchor is None:
+            if now - self._ref[1] >= self._anchor_period:
+                ev = self.torch.cuda.Event(enable_timing=True)
+                ev.record(self.d2h_stream)
+                self._anchor = ev
+        elif self._anchor.query():
+            self._ref = (self._anchor, now)
+            self._anchor = None
+
+    def clock_offset(self) -> float:
+        """Host time minus the GPU-clock time of an event recorded and
+        waited for now: the error of the current anchor (seconds)."""
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record(self.d2h_stream)
+        ev.synchronize()
+        return time.perf_counter() - self._gpu_time(ev)
 
     def _admit(self) -> None:
         torch = self.torch
@@ -204,35 +328,53 @@ class StreamServer:
             s = self.streams.get(fr.stream_id)
             if s is None:
                 raise KeyError(f"frame for unopened stream {fr.stream_id}")
+            fr.slices = -(-s.cfg.T // s.slice_samples)
             s.waiting.append(fr)
-        # oldest first across streams
-        order = sorted((s.waiting[0].t_arrival, sid) for sid, s in self.streams.items()
-                       if s.waiting)
-        for _, sid in order:
+        # slices of the oldest frame first, across streams, while slots last
+        while True:
+            head = [(s.waiting[0].t_arrival, sid) for sid, s in self.streams.items()
+                    if s.waiting]
+            if not head:
+                return
+            _, sid = min(head)
             s = self.streams[sid]
-            while s.waiting:
-                fr = s.waiting[0]
-                cfg = s.cfg
-                nb = frame_bytes(cfg)
-                if self.used + nb > self.budget:
-                    self.admission_waits += 1
-                    return          # keep arrival order: nothing younger overtakes
+            fr = s.waiting[0]
+            cfg = s.cfg
+            if fr.packed.is_cuda:
+                # already in HBM: the whole frame as one slice, nothing to copy
                 s.waiting.popleft()
-                self.used += nb
-                self.max_used = max(self.max_used, self.used)
-                fr.nbytes = nb
-                if fr.packed.is_cuda:       # already in HBM: nothing to copy
-                    fr.dev_packed, fr.dev_mask = fr.packed, fr.mask
-                    fr.ev_copied = None
-                    s.pending.append(fr)
-                    continue
-                with torch.cuda.stream(self.copy_stream):
-                    fr.dev_packed = fr.packed.to(self.device, non_blocking=True)
-                    fr.dev_mask = (fr.mask.to(self.device, non_blocking=True)
-                                   if fr.mask is not None else None)
-                    fr.ev_copied = torch.cuda.Event()
-                    fr.ev_copied.record(self.copy_stream)
-                s.pending.append(fr)
+                fr.slices = fr.copied = 1
+                s.pending.append(_Slice(fr, 0, cfg.T, fr.packed, fr.mask, None))
+                continue
+            k = self.pool.take()
+            if k < 0:
+                self.admission_waits += 1
+                return          # no slot: wait for a batch to finish
+            j = fr.copied
+            t0 = j * s.slice_samples
+            t1 = min(cfg.T, t0 + s.slice_samples)
+            dp = self.pool.packed(k, (t1 - t0, cfg.F, cfg.N))
+            dm = None
+            if fr.mask is not None:
+                b0, b1 = t0 // cfg.B, -(-t1 // cfg.B)
+                hm = self.pool.mask(k, (cfg.F, b1 - b0), host=True)
+                hm.copy_(fr.mask[:, b0:b1])     # host to pinned host, a few KB
+                dm = self.pool.mask(k, (cfg.F, b1 - b0))
+            with torch.cuda.stream(self.copy_stream):
+                if j == 0:
+                    fr.ev_copy_start = torch.cuda.Event(enable_timing=True)
+                    fr.ev_copy_start.record(self.copy_stream)
+                    fr.t_copy_issue = time.perf_counter()
+                dp.copy_(fr.packed[t0:t1], non_blocking=True)
+                if dm is not None:
+                    dm.copy_(hm, non_blocking=True)
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(self.copy_stream)
+            fr.copied += 1
+            if fr.copied == fr.slices:
+                fr.ev_copied = ev
+                s.waiting.popleft()
+            s.pending.append(_Slice(fr, t0, t1, dp, dm, ev, k))
 
     def _launch(self) -> bool:
         torch = self.torch
@@ -240,37 +382,38 @@ class StreamServer:
             return False
         batch = []
         for sid, s in self.streams.items():
-            if s.pending:
+            if s.pending and (s.pending[0].ev_copied is None or s.pending[0].ev_copied.query()):
                 batch.append((s, s.pending.popleft()))
         if not batch:
             return False
         cs = self.compute_stream
         items = []
-        for s, fr in batch:
-            if s.cfg.aligned:
+        for s, sl in batch:
+            fr = sl.frame
+            if s.cfg.aligned and fr.launched == 0:
                 w = fr.seq // s.cfg.frames_per_integration
                 if s.frames_in and w != s.window:
                     # a frame of a later window: the current one is over,
                     # short of the frames that never came
                     self._finish(s)
                 s.window = w
-            if fr.ev_copied is not None:
-                cs.wait_event(fr.ev_copied)
-            # the device tensors were made on the copy stream: keep their
-            # memory from being reused before the compute stream is done
-            fr.dev_packed.record_stream(cs)
-            if fr.dev_mask is not None:
-                fr.dev_mask.record_stream(cs)
+            if sl.ev_copied is not None:
+                cs.wait_event(sl.ev_copied)
             vis, cnt = s.acc[s.cur]
-            items.append((fr.dev_packed, fr.dev_mask, s.cfg.B, vis, cnt))
+            items.append((sl.packed, sl.mask, s.cfg.B, vis, cnt))
         xengine.accumulate_batch(items, handle=self.h, stream=cs)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record(cs)
-        self.inflight.append((ev, [fr for _, fr in batch]))
+        self.inflight.append((ev, [sl for _, sl in batch]))
         self.batches += 1
         self.batch_sizes.append(len(batch))
-        # integrations that this batch completes
-        for s, fr in batch:
+        # frames whose last slice this batch takes, and the integrations they
+        # complete
+        for s, sl in batch:
+            fr = sl.frame
+            fr.launched += 1
+            if fr.launched < fr.slices:
+                continue
             if s.frames_in == 0:
                 s.seq_first = fr.seq
             s.seq_last = fr.seq
@@ -296,10 +439,9 @@ class StreamServer:
         # the host copy of buffer k (two integrations ago) must have been
         # taken: its copy-out is long done, collect it
         if s.host_busy[k]:
-            s.ev_d2h[k].synchronize()
-            self._complete()
-        assert not s.host_busy[k]
+            s.host_free[k].wait()      # delivered long ago, in practice
         s.host_busy[k] = True
+        s.host_free[k].clear()
         hv, hc, ho = s.host[k]
         self.d2h_stream.wait_event(ev_norm)
         with torch.cuda.stream(self.d2h_stream):
@@ -309,8 +451,10 @@ class StreamServer:
             ev_d2h = torch.cuda.Event(enable_timing=True)
             ev_d2h.record(self.d2h_stream)
         s.ev_d2h[k] = ev_d2h
-        self.outgoing.append((ev_d2h, s, k, s.index, s.frames_in,
-                              (s.seq_first, s.seq_last, s.window if s.cfg.aligned else -1)))
+        with self._out_lock:
+            self._out_pending += 1
+        self._out_q.put((ev_d2h, s, k, s.index, s.frames_in,
+                         (s.seq_first, s.seq_last, s.window if s.cfg.aligned else -1)))
         s.index += 1
         s.frames_in = 0
         s.cur ^= 1
@@ -336,32 +480,55 @@ class StreamServer:
     def _complete(self) -> int:
         n = 0
         while self.inflight and self.inflight[0][0].query():
-            ev, frames = self.inflight.popleft()
+            ev, slices = self.inflight.popleft()
             t_done = self._gpu_time(ev)
-            for fr in frames:
+            for sl in slices:
+                if sl.slot >= 0:
+                    self.pool.give(sl.slot)
+                fr = sl.frame
+                cfg = self.streams[fr.stream_id].cfg
+                self.bytes_done += (sl.t1 - sl.t0) * cfg.F * cfg.N
+                self.samples_done += (sl.t1 - sl.t0) * cfg.F * cfg.N
+                fr.done += 1
+                if fr.done < fr.slices:
+                    continue
                 fr.t_done = t_done
                 self.latencies.append(t_done - fr.t_arrival)
-                self.used -= fr.nbytes
-                self.bytes_done += fr.nbytes
-                cfg = self.streams[fr.stream_id].cfg
-                self.samples_done += cfg.N * cfg.F * cfg.T
+                if fr.ev_copy_start is not None:
+                    t_start = self._gpu_time(fr.ev_copy_start)
+                    t_copied = self._gpu_time(fr.ev_copied)
+                else:
+                    t_start = t_copied = fr.t_arrival
+                # waiting before the bytes move, the copy, and the rest
+                self.breakdown.append((t_start - fr.t_arrival, t_copied - t_start,
+                                       t_done - t_copied))
+                self.done_frames.append((fr.stream_id, fr.seq, fr.t_arrival))
                 self.frames_done += 1
-                fr.dev_packed = fr.dev_mask = None
+                fr.packed = fr.mask = None
             n += 1
-        while self.outgoing and self.outgoing[0][0].query():
-            ev, s, k, index, frames, (q0, q1, win) = self.outgoing.popleft()
-            hv, hc, ho = s.host[k]
-            res = IntegrationResult(s.cfg.stream_id, index, frames, hv.numpy().copy(),
-                                    hc.numpy().copy(), ho.numpy().copy(), self._gpu_time(ev),
-                                    q0, q1, win)
+        return n
+
+    def _deliver(self) -> None:
+        """Delivery thread: per finished integration, wait for its copy-out,
+        copy it from the pinned buffers (torch copies release the
+        interpreter lock), free the buffers and hand the result over."""
+        while True:
+            ev, s, k, index, frames, (q0, q1, win) = self._out_q.get()
+            ev.synchronize()
+            hv, hc, ho = (t.clone() for t in s.host[k])
+            res = IntegrationResult(s.cfg.stream_id, index, frames, hv.numpy(), hc.numpy(),
+                                    ho.numpy(), self._gpu_time(ev), q0, q1, win)
             s.host_busy[k] = False
+            s.host_free[k].set()
             self.results[s.cfg.stream_id].append(res)
             if self.on_result is not None:
                 self.on_result(res)
-        return n
+            with self._out_lock:
+                self._out_pending -= 1
 
     def step(self) -> bool:
         """One scheduling pass; True if anything happened."""
+        self._reanchor()
         done = self._complete()
         self._admit()
         launched = False
@@ -370,7 +537,7 @@ class StreamServer:
         return bool(done) or launched
 
     def busy(self) -> bool:
-        return (not self.arrivals.empty() or bool(self.inflight) or bool(self.outgoing) or
+        return (not self.arrivals.empty() or bool(self.inflight) or self._out_pending > 0 or
                 any(s.pending or s.waiting for s in self.streams.values()))
 
     def sync(self) -> None:
@@ -389,7 +556,16 @@ class StreamServer:
 
     def stats(self, wall_s: float) -> dict:
         lat = np.array(self.latencies) * 1e3
+        bd = np.array(self.breakdown).reshape(-1, 3) * 1e3
+        parts = {}
+        if bd.size:
+            slow = bd[lat >= np.percentile(lat, 99)]
+            for k, name in enumerate(("wait", "copy", "finish")):
+                parts[name] = {"p50_ms": float(np.percentile(bd[:, k], 50)),
+                               "p99_ms": float(np.percentile(bd[:, k], 99)),
+                               "mean_in_slowest_1pct_ms": float(slow[:, k].mean())}
         return {
+            "latency_breakdown": parts,
             "frames": self.frames_done,
             "batches": self.batches,
             "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
@@ -501,9 +677,16 @@ class LoadResult:
 
 
 def _frame_pool(specs, distinct: int, B: int):
+    """``distinct`` frames per stream: one generated, the others derived
+    from it (synth.stream_frame_variant), which costs a copy rather than
+    a fresh draw of Gaussian noise."""
     from . import synth
-    return {s.stream_id: [synth.stream_frame(s, k, B) for k in range(distinct)]
-            for s in specs}
+    out = {}
+    for s in specs:
+        base = synth.stream_frame(s, 0, B)
+        out[s.stream_id] = [base] + [synth.stream_frame_variant(s, base, k)
+                                     for k in range(1, distinct)]
+    return out
 
 
 def run_load(specs, frames_per_stream: Optional[int] = None, integrations: int = 1,
@@ -511,15 +694,21 @@ def run_load(specs, frames_per_stream: Optional[int] = None, integrations: int =
              duration: Optional[float] = None,
              B: int = 256, device: int = 0, max_inflight: int = 2,
              device_resident: bool = False, seed: int = 0, pool=None,
-             handle: Optional[xengine.Handle] = None) -> LoadResult:
+             handle: Optional[xengine.Handle] = None, slot_bytes: int = 32 << 20,
+             pool_bytes: Optional[int] = None,
+             slice_samples: Optional[int] = None) -> LoadResult:
     """Offer each stream's frames with Poisson arrivals at ``speed`` times
     its rate (``speed`` = inf: all at once) and serve them.
 
     Each stream sends ``frames_per_stream`` frames (default: ``integrations``
     whole integrations; with ``duration``: as many as its rate offers in that
-    many seconds), cycling through ``distinct`` generated frames.
+    many seconds, at the arrival times of a Poisson process given that
+    count, i.e. sorted uniform times over the duration, so that the realised
+    rate matches the offered one), cycling through ``distinct`` frames.
     ``device_resident``: the frames are already in HBM (no host link), to
-    measure the serving loop's own sustained rate."""
+    measure the serving loop's own sustained rate.  ``slot_bytes``,
+    ``pool_bytes`` and ``slice_samples`` configure the server's frame pool
+    and time slices."""
     import torch
     pool = pool or _frame_pool(specs, distinct, B)
     dev = torch.device("cuda", device)
@@ -542,15 +731,17 @@ def run_load(specs, frames_per_stream: Optional[int] = None, integrations: int =
         rate = s.frame_rate * speed
         if duration is not None and np.isfinite(rate):
             n = max(1, int(round(rate * duration)))
+            t = np.sort(rng.uniform(0.0, duration, n))
         else:
             n = frames_per_stream or integrations * s.frames_per_integration
-        gaps = (rng.exponential(1.0 / rate, n) if np.isfinite(rate) else np.zeros(n))
-        t = np.cumsum(gaps)
+            gaps = (rng.exponential(1.0 / rate, n) if np.isfinite(rate) else np.zeros(n))
+            t = np.cumsum(gaps)
         k_pool = len(tens[s.stream_id])
         sequence[s.stream_id] = [k % k_pool for k in range(n)]
         arrivals += [(float(t[k]), s.stream_id, k) for k in range(n)]
     arrivals.sort()
-    server = StreamServer(hbm_budget, device, max_inflight, handle)
+    server = StreamServer(hbm_budget, device, max_inflight, handle, slot_bytes=slot_bytes,
+                          pool_bytes=pool_bytes, slice_samples=slice_samples)
     for s in specs:
         server.open(StreamConfig(s.stream_id, s.N, s.F, s.T, B, s.frames_per_integration))
     stop = threading.Event()
@@ -572,19 +763,28 @@ def run_load(specs, frames_per_stream: Optional[int] = None, integrations: int =
         stop.set()
 
     prod = threading.Thread(target=produce, daemon=True)
+    # the producer and the scheduling loop share the interpreter: hand the
+    # lock over every 100 us rather than every 5 ms, so that a frame is not
+    # handed over milliseconds late while the loop polls its events
+    switch = sys.getswitchinterval()
+    sys.setswitchinterval(1e-4)
     t_start = time.perf_counter()
-    prod.start()
-    server.serve(stop)
-    prod.join()
+    try:
+        prod.start()
+        server.serve(stop)
+        prod.join()
+    finally:
+        sys.setswitchinterval(switch)
     torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t_start
     st = server.stats(wall)
     st["wall_s"] = wall
+    st["clock_offset_ms"] = server.clock_offset() * 1e3
     st["offered_gbps"] = (sum(s.rate_bps for s in specs) * speed / 1e9
                           if np.isfinite(speed) else None)
-    # what the Poisson draw actually offered: its bytes over the span of the
-    # arrivals (a finite draw's last arrival falls before or after duration)
-    span = arrivals[-1][0] if arrivals else 0.0
+    # what the draw actually offered: its bytes over the span of the
+    # arrivals (the duration when given)
+    span = duration if duration is not None else (arrivals[-1][0] if arrivals else 0.0)
     bits = sum(8.0 * s.N * s.F * s.T * len(sequence[s.stream_id]) for s in specs)
     st["offered_realized_gbps"] = bits / span / 1e9 if span > 0 else None
     st["arrival_span_s"] = span

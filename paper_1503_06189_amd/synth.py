@@ -506,3 +506,18 @@ def stream_frame(spec: StreamSpec, index: int, B: int = 256, sigma: float = 2.5,
     fill_lost(packed, mask, B, "zero")
     return Frame(packed, mask, spec.N, spec.F, spec.T, B,
                  f"stream{spec.stream_id}_frame{index}", spec.seed)
+
+
+def stream_frame_variant(spec: StreamSpec, base: Frame, index: int, B: int = 256,
+                         burst: float = 4.0, cap: float = 0.10) -> Frame:
+    """Frame ``index`` of a stream derived from an already generated frame:
+    its samples rolled in time and across inputs by steps that depend on
+    the index, with a loss mask of its own (lost blocks zero).  The
+    statistics are the base frame's; the data differ from it."""
+    rng = np.random.default_rng([spec.seed, index, 1])
+    shift = (index * 1013) % max(1, spec.T)
+    packed = np.roll(np.roll(base.packed, shift, axis=0), (index * 37) % spec.N, axis=2)
+    mask = gilbert_elliott_mask(rng, spec.F, nblocks(spec.T, B), spec.loss_rate, burst, cap)
+    fill_lost(packed, mask, B, "zero")
+    return Frame(packed, mask, spec.N, spec.F, spec.T, B,
+                 f"stream{spec.stream_id}_frame{index}", spec.seed)
