@@ -68,6 +68,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def _device_info(torch) -> dict:
+    """Name, architecture, compute units and clock of the GPU measured."""
+    p = torch.cuda.get_device_properties(0)
+    out = {"name": p.name, "arch": getattr(p, "gcnArchName", None),
+           "compute_units": p.multi_processor_count,
+           "hbm_bytes": int(p.total_memory)}
+    clock = getattr(p, "clock_rate", None)
+    if clock:
+        out["clock_khz"] = int(clock)
+    return out
+
+
 def _pmc():
     """The committed rocprofv3 counter summary of the correlation call, if
     it was taken on the current kernel source; else None."""
@@ -753,6 +765,7 @@ def main():
             "executed": measured_execution(),
         },
         "kernel_ms": round(kern_ms, 5),
+        "device": _device_info(torch),
         "kernel_alg_hbm_gbps": round(alg_bytes / (kern_ms / 1e3) / 1e9, 1),
         "wall_s": round(t_wall, 4),
     }

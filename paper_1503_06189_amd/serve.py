@@ -283,6 +283,75 @@ class StreamServer:
         self.used -= s.resident_bytes
         del self.streams[stream_id]
 
+    def abort(self, stream_id: int) -> int:
+        """A stream that died mid-integration: drop its queued frames and its
+        open integration, return their slots, and close it; the other
+        streams go on untouched.  Returns the frames dropped."""
+        self.sync_launched(stream_id)
+        s = self.streams[stream_id]
+        dropped = len({id(f) for f in s.waiting} | {id(sl.frame) for sl in s.pending})
+        for sl in s.pending:
+            if sl.slot >= 0:
+                if sl.ev_copied is not None:
+                    sl.ev_copied.synchronize()
+                self.pool.give(sl.slot)
+        s.pending.clear()
+        s.waiting.clear()
+        s.frames_in = 0
+        self._drain_deliveries()
+        self.used -= s.resident_bytes
+        del self.streams[stream_id]
+        return dropped
+
+    def sync_launched(self, stream_id: int) -> None:
+        """Wait until every batch launched so far has completed."""
+        while self.inflight:
+            self.inflight[0][0].synchronize()
+            self._complete()
+
+    def _drain_deliveries(self) -> None:
+        while self._out_pending > 0:
+            time.sleep(50e-6)
+
+    # -- checkpoint / resume ------------------------------------------------
+
+    def checkpoint(self, path: str) -> None:
+        """Write every stream's open integration (sums, counts, samples and
+        the integration's bookkeeping) to an .npz file, after serving
+        everything submitted so far.  A server with the same streams open
+        continues from it with :meth:`resume`."""
+        import json
+        self.sync()
+        arrays, meta = {}, {}
+        for sid, s in self.streams.items():
+            vis, cnt = s.acc[s.cur]
+            snap = xengine.snapshot(vis, cnt, self.compute_stream)
+            arrays[f"vis_{sid}"] = snap["vis"]
+            arrays[f"count_{sid}"] = snap["count"]
+            meta[str(sid)] = {"cfg": dataclasses.asdict(s.cfg), "samples": snap["samples"],
+                              "frames_in": s.frames_in, "seq_first": s.seq_first,
+                              "seq_last": s.seq_last, "window": s.window, "index": s.index}
+        np.savez(path, meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8), **arrays)
+
+    def resume(self, path: str) -> None:
+        """Load a checkpoint into the open streams of the same ids and shapes;
+        their next frames continue the saved integrations."""
+        import json
+        self.sync()
+        with np.load(path, allow_pickle=False) as z:
+            meta = json.loads(z["meta"].tobytes().decode())
+            for sid_text, m in meta.items():
+                sid = int(sid_text)
+                s = self.streams.get(sid)
+                if s is None or dataclasses.asdict(s.cfg) != m["cfg"]:
+                    raise ValueError(f"stream {sid} is not open with the checkpoint's shape")
+                vis, cnt = s.acc[s.cur]
+                xengine.restore({"vis": z[f"vis_{sid}"], "count": z[f"count_{sid}"],
+                                 "samples": m["samples"]}, vis, cnt, self.compute_stream)
+                s.frames_in = m["frames_in"]
+                s.seq_first, s.seq_last = m["seq_first"], m["seq_last"]
+                s.window, s.index = m["window"], m["index"]
+
     # -- input --------------------------------------------------------------
 
     def submit(self, frame: Frame) -> None:

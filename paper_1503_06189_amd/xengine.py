@@ -106,6 +106,36 @@ def integrated_samples(vis) -> int:
         return _entry_count(vis.data_ptr())
 
 
+def snapshot(vis, count, stream=None) -> dict:
+    """Checkpoint of an integration in progress: its sums and counts copied to
+    host memory, with the samples integrated so far.  The integration state
+    is exactly the output plus the counts (Sec. II-C), so restoring the
+    snapshot into any accumulators of the same shape and continuing gives
+    the uninterrupted result (accumulation is linear in time)."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    with torch.cuda.stream(s):
+        v = vis.to("cpu", non_blocking=False)
+        c = count.to("cpu", non_blocking=False)
+    return {"vis": v.numpy(), "count": c.numpy(), "samples": integrated_samples(vis)}
+
+
+def restore(state: dict, vis, count, stream=None) -> None:
+    """Load a snapshot into ``vis``/``count`` (same shapes) on the device."""
+    import torch
+    v = torch.from_numpy(state["vis"])
+    c = torch.from_numpy(state["count"])
+    if tuple(v.shape) != tuple(vis.shape) or tuple(c.shape) != tuple(count.shape):
+        raise ValueError("snapshot shape differs from the accumulators")
+    s = torch.cuda.current_stream() if stream is None else stream
+    with torch.cuda.stream(s):
+        vis.copy_(v)
+        count.copy_(c)
+    s.synchronize()
+    with _integrated_lock:
+        _set_count(vis, int(state["samples"]))
+
+
 def _charge(pairs, call):
     """Run ``call`` (which returns an xe_status and raises on failure) only if
     adding T samples to each (vis, T) keeps every count within the bound;

@@ -255,3 +255,111 @@ def test_aligned_streams_combined_by_stream_id(srv, orc):
             assert list(back["stream_ids"]) == ids and int(back["window"]) == c.window
     # stream 5 lacked frame 0: its window-0 integration holds one frame
     assert comb.combined[0].frames == [2, 1, 2]
+
+
+def test_snapshot_restore_equals_uninterrupted(srv, orc):
+    """An integration split by a snapshot (device to host) and a restore
+    into other accumulators equals the uninterrupted one and the oracle of
+    the two frames concatenated in time."""
+    from paper_1503_06189_amd import xengine
+    a = synth.random_bytes_frame(seed=61, N=96, F=3, T=700, B=64, p_loss=0.1)
+    b = synth.random_bytes_frame(seed=62, N=96, F=3, T=900, B=64, p_loss=0.1)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    v1, c1 = xengine.new_accumulators(96, 3)
+    xengine.accumulate(dev(a.packed), dev(a.mask), 64, v1, c1)
+    snap = xengine.snapshot(v1, c1)
+    assert snap["samples"] == 700
+    v2, c2 = xengine.new_accumulators(96, 3)
+    xengine.restore(snap, v2, c2)
+    assert xengine.integrated_samples(v2) == 700
+    xengine.accumulate(dev(b.packed), dev(b.mask), 64, v2, c2)
+    xengine.accumulate(dev(b.packed), dev(b.mask), 64, v1, c1)
+    torch.cuda.synchronize()
+    assert np.array_equal(v1.cpu().numpy(), v2.cpu().numpy())
+    assert np.array_equal(c1.cpu().numpy(), c2.cpu().numpy())
+    ea, na = orc.correlate(a.packed, a.mask, 64)
+    eb, nb = orc.correlate(b.packed, b.mask, 64)
+    assert np.array_equal(v2.cpu().numpy().astype(np.int64), ea + eb)
+    assert np.array_equal(c2.cpu().numpy(), na + nb)
+
+
+def _serve_frames(server, frames, sid_seq):
+    from paper_1503_06189_amd.serve import Frame
+    for sid, q in sid_seq:
+        fr = frames[sid][q]
+        server.submit(Frame(sid, q, torch.from_numpy(fr.packed).cuda(),
+                            torch.from_numpy(fr.mask).cuda(), 0.0))
+        server.step()
+    server.sync()
+
+
+def test_checkpoint_resume_across_servers(srv, orc, tmp_path):
+    """Two streams integrate 3 frames each.  A server takes the first two
+    frames of every stream and writes a checkpoint; a fresh server opens the
+    same streams, resumes from it and takes the last frames: its results
+    equal an uninterrupted server's and the oracle's."""
+    from paper_1503_06189_amd.serve import StreamConfig, StreamServer
+    from paper_1503_06189_amd.synth import StreamSpec, stream_frame
+    specs = [StreamSpec(3, 64, 2, 512, 3, 0.05, 1e9, 7101),
+             StreamSpec(9, 128, 3, 512, 3, 0.05, 1e9, 7102)]
+    frames = {s.stream_id: [stream_frame(s, q, 64) for q in range(3)] for s in specs}
+    cfgs = [StreamConfig(s.stream_id, s.N, s.F, s.T, 64, 3) for s in specs]
+
+    def server():
+        sv = StreamServer(hbm_budget=1 << 30)
+        for c in cfgs:
+            sv.open(c)
+        return sv
+
+    whole = server()
+    _serve_frames(whole, frames, [(s.stream_id, q) for q in range(3) for s in specs])
+    first = server()
+    _serve_frames(first, frames, [(s.stream_id, q) for q in range(2) for s in specs])
+    assert not any(first.results.values())
+    path = str(tmp_path / "ckpt.npz")
+    first.checkpoint(path)
+    second = server()
+    second.resume(path)
+    _serve_frames(second, frames, [(s.stream_id, 2) for s in specs])
+    for s in specs:
+        (rw,), (rr,) = whole.results[s.stream_id], second.results[s.stream_id]
+        assert rr.frames == 3 and rr.index == rw.index == 0
+        assert np.array_equal(rr.vis, rw.vis) and np.array_equal(rr.count, rw.count)
+        assert np.array_equal(rr.out.view(np.uint32), rw.out.view(np.uint32))
+        ev = en = None
+        for fr in frames[s.stream_id]:
+            v, n = orc.correlate(fr.packed, fr.mask, 64)
+            ev = v if ev is None else ev + v
+            en = n if en is None else en + n
+        assert np.array_equal(rr.vis.astype(np.int64), ev) and np.array_equal(rr.count, en)
+
+
+def test_stream_dying_mid_integration(srv, orc, specs, pool):
+    """One of four streams dies after part of an integration: the server
+    drops its frames and open sums, returns its pool slots and closes it;
+    the other streams' results still equal the oracle."""
+    from paper_1503_06189_amd.serve import Frame, StreamConfig, StreamServer
+    server = StreamServer(hbm_budget=1 << 30, slice_samples=256)
+    for s in specs:
+        server.open(StreamConfig(s.stream_id, s.N, s.F, s.T, 256, s.frames_per_integration))
+    victim = specs[1].stream_id
+    seq = {s.stream_id: [k % 2 for k in range(s.frames_per_integration)] for s in specs}
+    for k in range(max(len(v) for v in seq.values())):
+        for s in specs:
+            if k >= len(seq[s.stream_id]) or (s.stream_id == victim and k >= 1):
+                continue
+            fr = pool[s.stream_id][seq[s.stream_id][k]]
+            server.submit(Frame(s.stream_id, k, torch.from_numpy(fr.packed).pin_memory(),
+                                torch.from_numpy(fr.mask).pin_memory(), 0.0))
+        server.step()
+        if k == 1:
+            server.abort(victim)
+    server.sync()
+    assert victim not in server.streams and not server.results.get(victim)
+    assert len(server.pool.free) == server.pool.n
+    for s in specs:
+        if s.stream_id == victim:
+            continue
+        (r,) = server.results[s.stream_id]
+        ev, en, eo = _expected(orc, s, pool, seq[s.stream_id], 0)
+        assert np.array_equal(r.count, en) and np.array_equal(r.vis.astype(np.int64), ev)
