@@ -234,6 +234,7 @@ class StreamServer:
         self._out_q: "queue.Queue" = queue.Queue()
         self._out_pending = 0
         self._out_lock = threading.Lock()
+        self._deliver_error: Optional[BaseException] = None
         self._deliverer = threading.Thread(target=self._deliver, daemon=True)
         self._deliverer.start()
         self.results: Dict[int, List[IntegrationResult]] = collections.defaultdict(list)
@@ -276,6 +277,7 @@ class StreamServer:
 
     def close(self, stream_id: int) -> None:
         """Forget a stream whose frames have all been integrated."""
+        self._take_arrivals()
         s = self.streams[stream_id]
         if s.pending or s.waiting or s.frames_in:
             raise RuntimeError(f"stream {stream_id} still has frames")
@@ -286,7 +288,9 @@ class StreamServer:
     def abort(self, stream_id: int) -> int:
         """A stream that died mid-integration: drop its queued frames and its
         open integration, return their slots, and close it; the other
-        streams go on untouched.  Returns the frames dropped."""
+        streams go on untouched.  Returns the frames dropped, those
+        submitted but not yet scheduled included."""
+        self._take_arrivals()
         self.sync_launched(stream_id)
         s = self.streams[stream_id]
         dropped = len({id(f) for f in s.waiting} | {id(sl.frame) for sl in s.pending})
@@ -312,6 +316,13 @@ class StreamServer:
     def _drain_deliveries(self) -> None:
         while self._out_pending > 0:
             time.sleep(50e-6)
+        self._raise_delivery_error()
+
+    def _raise_delivery_error(self) -> None:
+        err = self._deliver_error
+        if err is not None:
+            self._deliver_error = None
+            raise RuntimeError("delivering an integration result failed") from err
 
     # -- checkpoint / resume ------------------------------------------------
 
@@ -387,18 +398,23 @@ class StreamServer:
         ev.synchronize()
         return time.perf_counter() - self._gpu_time(ev)
 
-    def _admit(self) -> None:
-        torch = self.torch
+    def _take_arrivals(self) -> None:
+        """Move the frames handed over by :meth:`submit` to their streams'
+        queues."""
         while True:
             try:
                 fr = self.arrivals.get_nowait()
             except queue.Empty:
-                break
+                return
             s = self.streams.get(fr.stream_id)
             if s is None:
                 raise KeyError(f"frame for unopened stream {fr.stream_id}")
             fr.slices = -(-s.cfg.T // s.slice_samples)
             s.waiting.append(fr)
+
+    def _admit(self) -> None:
+        torch = self.torch
+        self._take_arrivals()
         # slices of the oldest frame first, across streams, while slots last
         while True:
             head = [(s.waiting[0].t_arrival, sid) for sid, s in self.streams.items()
@@ -580,23 +596,40 @@ class StreamServer:
     def _deliver(self) -> None:
         """Delivery thread: per finished integration, wait for its copy-out,
         copy it from the pinned buffers (torch copies release the
-        interpreter lock), free the buffers and hand the result over."""
+        interpreter lock), free the buffers and hand the result over.
+        An exception (a failing callback, say) is kept for the scheduling
+        thread to raise; the buffers are freed and the result counted as
+        delivered either way, so nothing waits for it forever."""
         while True:
             ev, s, k, index, frames, (q0, q1, win) = self._out_q.get()
-            ev.synchronize()
-            hv, hc, ho = (t.clone() for t in s.host[k])
-            res = IntegrationResult(s.cfg.stream_id, index, frames, hv.numpy(), hc.numpy(),
-                                    ho.numpy(), self._gpu_time(ev), q0, q1, win)
-            s.host_busy[k] = False
-            s.host_free[k].set()
-            self.results[s.cfg.stream_id].append(res)
-            if self.on_result is not None:
-                self.on_result(res)
-            with self._out_lock:
-                self._out_pending -= 1
+            freed = False
+            try:
+                ev.synchronize()
+                hv, hc, ho = (t.clone() for t in s.host[k])
+                res = IntegrationResult(s.cfg.stream_id, index, frames, hv.numpy(), hc.numpy(),
+                                        ho.numpy(), self._gpu_time(ev), q0, q1, win)
+                # free buffer k before the callback, which may take long; the
+                # scheduling thread may then reuse it at once
+                s.host_busy[k] = False
+                s.host_free[k].set()
+                freed = True
+                self.results[s.cfg.stream_id].append(res)
+                if self.on_result is not None:
+                    self.on_result(res)
+            except BaseException as e:    # raised again by the scheduling thread
+                if self._deliver_error is None:
+                    self._deliver_error = e
+            finally:
+                if not freed:
+                    s.host_busy[k] = False
+                    s.host_free[k].set()
+                with self._out_lock:
+                    self._out_pending -= 1
 
     def step(self) -> bool:
-        """One scheduling pass; True if anything happened."""
+        """One scheduling pass; True if anything happened.  Raises
+        RuntimeError if a result could not be delivered."""
+        self._raise_delivery_error()
         self._reanchor()
         done = self._complete()
         self._admit()
@@ -614,6 +647,7 @@ class StreamServer:
         while self.busy():
             if not self.step():
                 time.sleep(20e-6)
+        self._raise_delivery_error()
 
     def serve(self, stop: threading.Event, idle_sleep: float = 20e-6) -> None:
         """Scheduling loop until `stop` is set and nothing is left."""

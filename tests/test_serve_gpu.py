@@ -363,3 +363,75 @@ def test_stream_dying_mid_integration(srv, orc, specs, pool):
         (r,) = server.results[s.stream_id]
         ev, en, eo = _expected(orc, s, pool, seq[s.stream_id], 0)
         assert np.array_equal(r.count, en) and np.array_equal(r.vis.astype(np.int64), ev)
+
+
+def _submit(server, spec, fr, seq):
+    from paper_1503_06189_amd.serve import Frame
+    server.submit(Frame(spec.stream_id, seq, torch.from_numpy(fr.packed).pin_memory(),
+                        torch.from_numpy(fr.mask).pin_memory(), 0.0))
+
+
+def test_failing_result_callback_is_raised_not_waited_for(srv, orc, specs, pool):
+    """A result callback that raises: sync() raises RuntimeError with the
+    callback's error as its cause instead of waiting forever for the result
+    to be delivered; the result is still kept, and the server goes on."""
+    from paper_1503_06189_amd.serve import StreamConfig, StreamServer
+    calls = []
+
+    def on_result(res):
+        calls.append(res.index)
+        if len(calls) == 1:
+            raise ValueError("the consumer failed")
+
+    server = StreamServer(hbm_budget=1 << 30, on_result=on_result)
+    s = specs[0]
+    server.open(StreamConfig(s.stream_id, s.N, s.F, s.T, 256, 1))
+    fr = pool[s.stream_id][0]
+    _say(f"failing callback, stream {s.stream_id} N={s.N} F={s.F}")
+    _submit(server, s, fr, 0)
+    with pytest.raises(RuntimeError) as err:
+        server.sync()
+    assert isinstance(err.value.__cause__, ValueError)
+    _submit(server, s, fr, 1)
+    server.sync()
+    assert calls == [0, 1]
+    ev, en = orc.correlate(fr.packed, fr.mask, fr.B)
+    assert [r.index for r in server.results[s.stream_id]] == [0, 1]
+    for r in server.results[s.stream_id]:
+        assert np.array_equal(r.count, en) and np.array_equal(r.vis.astype(np.int64), ev)
+
+
+def test_abort_and_close_see_frames_not_yet_scheduled(srv, orc, specs, pool):
+    """Frames submitted for a stream aborted before the scheduler took them
+    are dropped with it and counted, and later passes do not trip over
+    them; close() of a stream with such frames refuses.  The surviving
+    stream's integration equals the oracle."""
+    from paper_1503_06189_amd.serve import StreamConfig, StreamServer
+    server = StreamServer(hbm_budget=1 << 30)
+    a, b, c = specs[0], specs[1], specs[2]
+    for s in (a, b, c):
+        server.open(StreamConfig(s.stream_id, s.N, s.F, s.T, 256, 2))
+    for k in range(2):
+        for s in (a, b):
+            _submit(server, s, pool[s.stream_id][k], k)
+    _submit(server, c, pool[c.stream_id][0], 0)
+    _say(f"abort {a.stream_id} with 2 unscheduled frames")
+    assert server.abort(a.stream_id) == 2
+    with pytest.raises(RuntimeError):
+        server.close(c.stream_id)
+    server.flush(c.stream_id)
+    server.sync()
+    assert a.stream_id not in server.streams and not server.results.get(a.stream_id)
+    (r,) = server.results[b.stream_id]
+    vis = cnt = 0
+    for k in range(2):
+        fr = pool[b.stream_id][k]
+        v, n = orc.correlate(fr.packed, fr.mask, fr.B)
+        vis, cnt = vis + v, cnt + n
+    assert np.array_equal(r.count, cnt) and np.array_equal(r.vis.astype(np.int64), vis)
+    (rc,) = server.results[c.stream_id]
+    fr = pool[c.stream_id][0]
+    v, n = orc.correlate(fr.packed, fr.mask, fr.B)
+    assert rc.frames == 1 and np.array_equal(rc.vis.astype(np.int64), v)
+    server.close(c.stream_id)
+    assert len(server.pool.free) == server.pool.n
