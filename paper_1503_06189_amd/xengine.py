@@ -121,10 +121,19 @@ def snapshot(vis, count, stream=None) -> dict:
 
 
 def restore(state: dict, vis, count, stream=None) -> None:
-    """Load a snapshot into ``vis``/``count`` (same shapes) on the device."""
+    """Load a snapshot into ``vis``/``count`` (same shapes) on the device.
+    Raises ValueError for a snapshot of another shape or element type, or
+    whose sample count lies outside 0 .. the int32 integration bound."""
+    import numpy as np
     import torch
-    v = torch.from_numpy(state["vis"])
-    c = torch.from_numpy(state["count"])
+    sv, sc = np.asarray(state["vis"]), np.asarray(state["count"])
+    if sv.dtype != np.int32 or sc.dtype != np.int64:
+        raise ValueError(f"snapshot types {sv.dtype}/{sc.dtype}, expected int32/int64")
+    samples = int(state["samples"])
+    if not 0 <= samples <= XE_MAX_SAMPLES:
+        raise ValueError(f"snapshot of {samples} samples, outside 0..{XE_MAX_SAMPLES}")
+    v = torch.from_numpy(np.ascontiguousarray(sv))
+    c = torch.from_numpy(np.ascontiguousarray(sc))
     if tuple(v.shape) != tuple(vis.shape) or tuple(c.shape) != tuple(count.shape):
         raise ValueError("snapshot shape differs from the accumulators")
     s = torch.cuda.current_stream() if stream is None else stream
@@ -133,7 +142,7 @@ def restore(state: dict, vis, count, stream=None) -> None:
         count.copy_(c)
     s.synchronize()
     with _integrated_lock:
-        _set_count(vis, int(state["samples"]))
+        _set_count(vis, samples)
 
 
 def _charge(pairs, call):
