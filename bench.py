@@ -269,6 +269,7 @@ def batched_leg(torch, reps: int):
             xengine.accumulate(*it, handle=h, stream=stream)
 
     choice = tune.tune(items, handle=h)
+    entry = tune.lookup(items) or {}
     plan = xengine.BatchPlan(items, chunk_steps=choice.chunk_steps, handle=h,
                              geometry=choice.geometry)
     g = torch.cuda.CUDAGraph()
@@ -310,6 +311,10 @@ def batched_leg(torch, reps: int):
         "mfma_frac": round(ops / (ms_graph / 1e3) / 1e12 / MFMA_INT8_PEAK_TOPS, 4),
         "chunk_steps": choice.chunk_steps,
         "geometry": choice.geometry,
+        # the tuner's fastest plan per tile geometry (graph-free plan runs)
+        "tuned_best_ms_by_geometry": {g: round(v, 4)
+                                      for g, v in tune.best_by_geometry(entry).items()},
+        "tuned_plans": len(entry.get("timings_ms", {})),
         "exact_vs_plain": bool(exact),
     }
 

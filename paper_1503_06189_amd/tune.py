@@ -98,6 +98,31 @@ def geometries(shapes: Sequence[Tuple[int, int, int, int]]) -> List[str]:
     return ["super", "halves"] if any(n <= 128 for n, _, _, _ in shapes) else ["auto"]
 
 
+def _key(items: Sequence[Tuple]) -> Tuple[str, List[Tuple[int, int, int, int]]]:
+    dev = items[0][0].device
+    shapes = [(int(p.shape[2]), int(p.shape[1]), int(p.shape[0]), int(B))
+              for p, m, B, v, c in items]
+    return f"{_arch(dev.index)}|{signature(shapes)}", shapes
+
+
+def lookup(items: Sequence[Tuple], path: Optional[str] = None) -> Optional[dict]:
+    """The cached tuning entry of this batch (its choice and every timing),
+    or None."""
+    if not items:
+        return None
+    hit = load_cache(path).get(_key(items)[0])
+    return hit if hit is not None and hit.get("version") == CACHE_VERSION else None
+
+
+def best_by_geometry(entry: dict) -> Dict[str, float]:
+    """Fastest timing (ms) per geometry of a cached tuning entry."""
+    best: Dict[str, float] = {}
+    for name, ms in entry.get("timings_ms", {}).items():
+        geom = name.split("/")[0]
+        best[geom] = min(best.get(geom, float("inf")), float(ms))
+    return best
+
+
 def tune(items: Sequence[Tuple], handle: Optional[xengine.Handle] = None,
          reps: int = 5, use_cache: bool = True, path: Optional[str] = None) -> Choice:
     """Best (chunk length, geometry) for a batch of (packed, mask, B, vis,
@@ -106,9 +131,7 @@ def tune(items: Sequence[Tuple], handle: Optional[xengine.Handle] = None,
     if not items:
         return Choice(0, "auto")
     dev = items[0][0].device
-    shapes = [(int(p.shape[2]), int(p.shape[1]), int(p.shape[0]), int(B))
-              for p, m, B, v, c in items]
-    key = f"{_arch(dev.index)}|{signature(shapes)}"
+    key, shapes = _key(items)
     if use_cache:
         hit = load_cache(path).get(key)
         if hit is not None and hit.get("version") == CACHE_VERSION:

@@ -46,3 +46,11 @@ def test_old_cache_entries_are_not_used(tmp_path):
     assert tune.load_cache(path)["k"].get("version") != tune.CACHE_VERSION
     c = tune.Choice(300, "halves")
     assert (c.chunk_steps, c.geometry) == (300, "halves")
+
+
+def test_best_by_geometry_takes_each_geometrys_fastest_plan():
+    from paper_1503_06189_amd import tune
+    entry = {"timings_ms": {"super/256": 1.5, "super/512": 1.2, "halves/256": 1.3,
+                            "halves/512": 1.4}}
+    assert tune.best_by_geometry(entry) == {"super": 1.2, "halves": 1.3}
+    assert tune.best_by_geometry({}) == {}
