@@ -569,6 +569,29 @@ def pin_time_shift(orc):
     assert synth.unpack_flags(fo, N)[:5].all() and not synth.unpack_flags(fo, N)[5:].any()
 
 
+def pin_time_shift_aligns_delayed_copy(orc):
+    """What the shift is for: input 1 carries input 0's signal D samples
+    later, and shifting input 1 by -D lines the two up.  Then the (0, 1)
+    visibility over the frame is input 0's autocorrelation over the
+    samples both still hold (the first T - D), real, with zero imaginary
+    part; unshifted it is not.  Input 1's last D samples are flagged."""
+    rng = np.random.default_rng(71)
+    T, F, N, D = 64, 2, 4, 9
+    packed = rng.integers(0, 256, (T, F, N), dtype=np.uint8)
+    packed[D:, :, 1] = packed[:T - D, :, 0]
+    d = np.zeros(N, np.int32)
+    d[1] = -D
+    out, fo = orc.time_shift(packed, None, d)
+    vs, _ = orc.correlate(out)
+    auto, _ = orc.correlate(packed[:T - D])
+    assert np.array_equal(vs[:, 1], auto[:, 0])     # pair (0, 1) vs pair (0, 0)
+    assert (vs[:, 1, 1] == 0).all() and (vs[:, 1, 0] > 0).all()
+    vu, _ = orc.correlate(packed)
+    assert not np.array_equal(vu[:, 1], auto[:, 0])
+    fb = synth.unpack_flags(fo, N)
+    assert fb[T - D:, :, 1].all() and not fb[:T - D, :, 1].any() and not fb[:, :, 0].any()
+
+
 PINS = [
     pin_decode_roundtrip,
     pin_tri_index,
@@ -589,4 +612,5 @@ PINS = [
     pin_assemble_roundtrip,
     pin_assemble_faults,
     pin_time_shift,
+    pin_time_shift_aligns_delayed_copy,
 ]
