@@ -258,6 +258,9 @@ xe_status xe_accumulate_batch(xe_handle h, const xe_instance *inst,
  * HIP graph: xe_batch_run only enqueues kernels (no copies, no host
  * synchronisation, no memset).  chunk_steps = time-chunk length in 32-sample
  * steps (0: automatic; the tuner in the Python package picks it).  The
+ * halves-geometry instances, which drain in a launch of their own, take
+ * shorter chunks when theirs would leave compute units idle: about their
+ * total work / compute units, at least 32 steps and at most chunk_steps.  The
  * plan keeps the instances' pointers: the caller keeps those buffers alive
  * and refills them between runs.  xe_batch_plan synchronises the device
  * upload; *plan_id receives the plan. */

@@ -282,18 +282,26 @@ size_t plan_bytes(const BatchPlan &p) {
 // Work items of a batch: every (instance, channel, group, time chunk), with
 // time chunks of about `chunk_steps` 32-sample steps (0: enough items for
 // about four per compute unit), longest first so the queue drains evenly.
+// Fills `plan` with the items of the batch: time chunks of `chunk_steps`
+// 32-sample steps, and of `small_chunk` steps for the halves-geometry
+// instances, which run in a launch of their own.
+xe_status fill_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int32_t chunk_steps,
+                     int32_t small_chunk, int halves, size_t ws_bytes, BatchPlan *plan);
+
 xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int n_cu,
                       int32_t chunk_steps, size_t ws_bytes, BatchPlan *plan) {
     if (n_inst < 0 || (n_inst > 0 && !inst)) return fail(h, XE_ERR_ARG, "bad batch arguments");
     if (chunk_steps < 0) return fail(h, XE_ERR_ARG, "chunk_steps must be >= 0");
     const int halves = halves_of(h->geometry);
-    int64_t work = 0;
+    int64_t work = 0, small_work = 0;
     for (int32_t k = 0; k < n_inst; ++k) {
         const xe_instance &x = inst[k];
         xe_status s = check_frame(h, x.packed, x.N, x.F, x.T, x.B, x.vis, x.count);
         if (s != XE_OK) return s;
         int nb = xe::ceil_div(x.N, xe::kBlk);
-        work += (int64_t)x.F * xe::groups_per_channel(nb) * xe::ceil_div(x.T, xe::kStep);
+        const int64_t w = (int64_t)x.F * xe::groups_per_channel(nb) * xe::ceil_div(x.T, xe::kStep);
+        work += w;
+        if (xe::use_halves(halves, nb) && aligned(x.packed, 4) && x.N % 4 == 0) small_work += w;
     }
     // instances of one launch update their sums without atomics, so their
     // output ranges must be disjoint
@@ -317,6 +325,23 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
         int64_t c = work / (4 * (int64_t)n_cu);
         chunk_steps = (int)std::max<int64_t>(32, std::min<int64_t>(c, xe::kMaxStepsPerChunk));
     }
+    // The halves-geometry items drain in a launch of their own after the
+    // others: with the common chunk length a few long items would hold it
+    // while most compute units idle, so their chunks are cut to about one
+    // item per compute unit (never longer than the common length, at least
+    // 32 steps), unless the extra chunk sums would not fit the workspace.
+    const int32_t small_chunk = (int32_t)std::max<int64_t>(
+        32, std::min<int64_t>(chunk_steps, (small_work + n_cu - 1) / n_cu));
+    if (small_chunk < chunk_steps) {
+        xe_status s = fill_batch(h, inst, n_inst, chunk_steps, small_chunk, halves, ws_bytes, plan);
+        if (s != XE_ERR_WORKSPACE) return s;
+        *plan = BatchPlan();
+    }
+    return fill_batch(h, inst, n_inst, chunk_steps, chunk_steps, halves, ws_bytes, plan);
+}
+
+xe_status fill_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int32_t chunk_steps,
+                     int32_t small_chunk, int halves, size_t ws_bytes, BatchPlan *plan) {
     plan->chunk_steps = chunk_steps;
     struct Cost {
         int64_t steps;
@@ -333,7 +358,8 @@ xe_status build_batch(xe_handle h, const xe_instance *inst, int32_t n_inst, int 
         const int G = xe::groups_per_channel(nb);
         const int steps = xe::ceil_div(x.T, xe::kStep);
         const int64_t max_sps = xe::max_steps_per_chunk(x.F, x.N);
-        int sps = (int)std::min<int64_t>(std::min<int64_t>(chunk_steps, steps), max_sps);
+        const int32_t cs = xe::use_halves(halves, nb) ? small_chunk : chunk_steps;
+        int sps = (int)std::min<int64_t>(std::min<int64_t>(cs, steps), max_sps);
         int splits = xe::ceil_div(steps, sps);
         sps = std::min<int>(xe::round_steps(xe::ceil_div(steps, splits)), (int)max_sps);
         splits = xe::ceil_div(steps, sps);

@@ -99,28 +99,46 @@ def test_batch_checks(L, h):
     assert L.xe_accumulate_batch(h, None, 2, None) == xe.XE_ERR_ARG
 
 
+def _model_items(shapes, chunk, n_cu=256):
+    """Work items of a batch in the default (halves) geometry: F * groups *
+    time chunks per instance, where instances of N <= 128 (their own
+    launch) take chunks of about their total work / n_cu steps, between 32
+    and the common length."""
+    def work(N, F, T):
+        nb = -(-N // 32)
+        return F * (-(-nb // 8)) ** 2 * -(-T // 32)
+    small_work = sum(work(N, F, T) for N, F, T, B in shapes if N <= 128)
+    small_chunk = max(32, min(chunk, -(-small_work // n_cu)))
+    items = 0
+    for N, F, T, B in shapes:
+        nb = -(-N // 32)
+        G = (-(-nb // 8)) ** 2
+        steps = -(-T // 32)
+        sps = min(small_chunk if N <= 128 else chunk, steps)
+        items += F * G * -(-steps // sps)
+    return items, small_chunk
+
+
 def test_batch_query_work_list():
     """Work items = sum over instances of F * groups * time chunks; the
-    automatic chunk length gives about four items per compute unit."""
+    automatic chunk length gives about four items per compute unit, and the
+    halves-geometry instances (N <= 128), which drain in a launch of their
+    own, about one per compute unit."""
     import random
     rng = random.Random(7)
     shapes = [(rng.choice([64, 128, 256, 512, 1024]), 1, 256 * rng.randint(4, 256), 256)
               for _ in range(128)]
     info = xe.batch_query(shapes, n_cu=256)
     assert info.instances == 128 and info.unaligned == 0
-    items = 0
-    work = 0
-    for N, F, T, B in shapes:
-        nb = -(-N // 32)
-        G = (-(-nb // 8)) ** 2
-        steps = -(-T // 32)
-        work += F * G * steps
-        sps = min(info.chunk_steps, steps)
-        splits = -(-steps // sps)
-        items += F * G * splits
-    assert info.items == items
+    work = sum(F * (-(-(-(-N // 32)) // 8)) ** 2 * -(-T // 32) for N, F, T, B in shapes)
     assert info.chunk_steps == max(32, work // (4 * 256))
-    assert 256 * 3 <= info.items <= 256 * 6
+    items, small_chunk = _model_items(shapes, info.chunk_steps)
+    assert info.items == items
+    assert small_chunk < info.chunk_steps
+    small = sum(1 for N, F, T, B in shapes if N <= 128)
+    small_items = items - _model_items([x for x in shapes if x[0] > 128], info.chunk_steps)[0]
+    assert small <= small_items and 256 <= small_items <= 256 + small
+    assert 256 * 3 <= info.items <= 256 * 7
     # an explicit chunk length
     info2 = xe.batch_query(shapes, n_cu=256, chunk_steps=2 * info.chunk_steps)
     assert info2.chunk_steps == 2 * info.chunk_steps and info2.items < info.items
